@@ -1,0 +1,396 @@
+"""Hybrid lattice Boltzmann step with the total-energy equation, FP64, on the CPU.
+
+Test infrastructure only (see oracle/__init__.py).
+
+Follows Sec. 2.2 and Appendix A of the paper:
+  Eq. (6)     fully discrete LBE in f-bar form, pull streaming
+  Eq. (7)     force populations F_i
+  Eqs. (8-9)  density and (half-force corrected) momentum
+  Eqs. (10-11) total-energy equation and its flux
+  Eq. (A.3)   equilibrium with the rest-population temperature term and the 3r cubic term
+  Eq. (A.4)   regularised off-equilibrium populations
+  Eq. (A.7)   hybrid recursive Pi^(2) (weight sigma, populations vs finite differences)
+  Eq. (A.8)   recursive Pi^(3)
+  Eq. (A.9)   second-order Hermite moment of the force a^F
+  Eq. (A.10)  discrete operators delta_t (forward) and delta_alpha (backward)
+  Eqs. (A.11-A.13) LB-consistent mass and momentum face fluxes
+  Eqs. (A.14-A.16) MUSCL-Hancock linear face operator
+
+Lattice units: dx = dt = 1, temperatures in units of T_ref (theta = T), R = c_s^2 = 1/3.
+
+Arrays: a scalar field has the grid shape (ny, nx) in 2D or (nz, ny, nx) in 3D
+(x fastest); populations are (Q, *grid); vectors (D, *grid); tensors (D, D, *grid).
+Neighbour access wraps periodically in every direction; the inflow/outflow
+closure then overwrites its columns (see `apply_closure`).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+
+
+@dataclass
+class Params:
+    """Physical and numerical parameters in lattice units."""
+    mu: float                       # dynamic viscosity (constant)
+    lam: float                      # thermal conductivity
+    gamma: float = 1.4              # Sec. 3.4: gamma = 1.4
+    sigma: float = 0.98             # HRR weight of Eq. (A.7), set to 0.98 in the paper
+    rho_inf: float = 1.0
+    u_inf: tuple = (0.0, 0.0, 0.0)
+    T_inf: float = 1.0
+    bc: str = 'periodic'            # 'periodic' or 'inflow_outflow' (closure along x)
+    with_aC: bool = True            # lattice third-order correction inside a^F, Eq. (A.9)
+    tau_theta: bool = False         # alternative reading: tau = mu/(rho cs2 theta)
+    dt_form: str = 'euler'          # d/dt[rho(1-theta)] in Eq. (A.9): 'euler' or 'backward'
+
+    @property
+    def R(self):
+        return 1.0 / 3.0
+
+    @property
+    def Cv(self):
+        return self.R / (self.gamma - 1.0)
+
+    @property
+    def Cp(self):
+        return self.gamma * self.R / (self.gamma - 1.0)
+
+
+@dataclass
+class State:
+    f: np.ndarray       # (Q, *grid) populations f-bar
+    rhoE: np.ndarray    # (*grid) total energy density
+    H1: np.ndarray      # (*grid) [rho (1 - theta)] of the previous step
+    H2: np.ndarray      # (D, D, *grid) deviatoric sum_i (c c - delta c^2/D) F_i of the previous step
+    step: int = 0
+
+    def copy(self):
+        return State(self.f.copy(), self.rhoE.copy(), self.H1.copy(), self.H2.copy(), self.step)
+
+
+# ----------------------------------------------------------------------------- helpers
+
+def axis_of(D, a):
+    """Grid axis holding spatial direction a (x fastest = last axis)."""
+    return D - 1 - a
+
+
+def at(arr, offset, D):
+    """Value of a field (leading non-grid axes allowed) at x + offset, periodic."""
+    out = arr
+    lead = arr.ndim - D
+    for a, s in enumerate(offset):
+        if s:
+            out = np.roll(out, -int(s), axis=lead + axis_of(D, a))
+    return out
+
+
+def unit(D, a, s=1):
+    e = [0] * D
+    e[a] = s
+    return e
+
+
+# ----------------------------------------------------------------------------- moments
+
+def density_momentum(lat, f):
+    """Eqs. (8)-(9) without the force: rho = sum f, j = sum c f."""
+    rho = f.sum(axis=0)
+    j = np.einsum('ia,i...->a...', lat.c.astype(np.float64), f)
+    return rho, j
+
+
+def predicted_macros(lat, prm, f, rhoE):
+    """Predicted (force-free) variables of the current state, Sec. 2.5 step 1.
+
+    rho* = sum f, j* = sum c f, u* = j*/rho*, T* from rho E = rho(|u*|^2/2 + Cv T*).
+    """
+    rho, j = density_momentum(lat, f)
+    u = j / rho
+    T = (rhoE / rho - 0.5 * (u * u).sum(axis=0)) / prm.Cv
+    return rho, j, u, T
+
+
+def equilibrium(lat, rho, u, theta):
+    """Eq. (A.3). The third-order term is the orthogonal projection on the 3r basis."""
+    D, cs2 = lat.D, lat.cs2
+    cf = lat.c.astype(np.float64)
+    w = lat.w.reshape((-1,) + (1,) * rho.ndim)
+    delta0 = np.zeros(lat.Q)
+    delta0[0] = 1.0
+    rest = ((lat.w - delta0) / lat.w).reshape(w.shape)
+    cu = np.einsum('ia,a...->i...', cf, u)
+    uu = u[:, None] * u[None, :]
+    h2uu = np.einsum('iab,ab...->i...', lat.h2, uu)
+    uuu = u[:, None, None] * u[None, :, None] * u[None, None, :]
+    a3r = lat.tensor3_to_3r(rho * uuu)                         # K x grid
+    h3 = np.einsum('ik,k,k...->i...', lat.h3r, 1.0 / lat.h3r_norm, a3r)
+    return w * (rho + rest * rho * (theta - 1.0) + cu * rho / cs2 + h2uu * rho / (2 * cs2 ** 2) + h3)
+
+
+def regularized_neq(lat, Pi, u):
+    """Eq. (A.4) with Pi^(3) from Eq. (A.8), projected on the 3r basis."""
+    cs2 = lat.cs2
+    w = lat.w.reshape((-1,) + (1,) * (Pi.ndim - 2))
+    h2pi = np.einsum('iab,ab...->i...', lat.h2, Pi)
+    Pi3 = (u[:, None, None] * Pi[None, :, :] + u[None, :, None] * Pi.transpose((1, 0) + tuple(range(2, Pi.ndim)))[:, None, :]
+           + u[None, None, :] * Pi[:, :, None])
+    # Pi3[a,b,g] = u_a Pi_bg + u_b Pi_ga + u_g Pi_ab
+    pi3r = lat.tensor3_to_3r(Pi3)
+    h3 = np.einsum('ik,k,k...->i...', lat.h3r, 1.0 / lat.h3r_norm, pi3r)
+    return w * (h2pi / (2 * cs2 ** 2)) + w * h3
+
+
+def force_populations(lat, fu, aF):
+    """Eq. (7): F_i = w_i [H1_i . f_u / cs^2 + H2_i : a^F / (2 cs^4)]."""
+    cs2 = lat.cs2
+    w = lat.w.reshape((-1,) + (1,) * (fu.ndim - 1))
+    return w * (np.einsum('ia,a...->i...', lat.h1, fu) / cs2
+                + np.einsum('iab,ab...->i...', lat.h2, aF) / (2 * cs2 ** 2))
+
+
+def deviatoric_second_moment(lat, g):
+    """sum_i (c_ia c_ib - delta_ab c_i^2 / D) g_i  (the projector of Eq. (A.7))."""
+    cf = lat.c.astype(np.float64)
+    dev = cf[:, :, None] * cf[:, None, :] - np.eye(lat.D)[None] * (cf * cf).sum(1)[:, None, None] / lat.D
+    return np.einsum('iab,i...->ab...', dev, g)
+
+
+def central_gradient(u, D):
+    """du[a, b] = d u_a / d x_b, second-order central differences (periodic)."""
+    return np.stack([np.stack([(at(u[a], unit(D, b, 1), D) - at(u[a], unit(D, b, -1), D)) / 2.0
+                               for b in range(D)]) for a in range(D)])
+
+
+# ----------------------------------------------------------------------------- collision
+
+def collide(lat, prm, st, fib):
+    """Steps 5 of Sec. 2.5 up to the post-collision populations.
+
+    Returns a dict with f^col and the cell quantities the flux stage needs.
+    fib: (D, *grid) Eulerian momentum forcing f^IB (zero away from the body).
+    """
+    D, cs2 = lat.D, lat.cs2
+    rho, j, ustar, T = predicted_macros(lat, prm, st.f, st.rhoE)
+    theta = T                                            # T_ref = 1
+    u = (j + 0.5 * fib) / rho                            # Eq. (9)
+    du = central_gradient(u, D)
+    div = sum(du[a, a] for a in range(D))
+    eye = np.eye(D).reshape((D, D) + (1,) * rho.ndim)
+
+    # Eq. (A.9): a^F. The time derivative of rho(1 - theta) is evaluated from
+    # the first-order (Euler) balance laws, d rho/dt = -div(rho u) and
+    # d p/dt = -u.grad p - gamma p div u with p = rho cs^2 theta, by central
+    # differences ('euler'); the alternative 'backward' uses the stored previous
+    # value. a^C corrects the lattice's missing diagonal third-order equilibrium
+    # moment rho u_a^3.
+    g_now = rho * (1.0 - theta)
+    if prm.dt_form == 'euler':
+        p_cs2 = rho * theta                              # p / cs^2
+        ddiv_rhou = sum((at(rho * u[a], unit(D, a, 1), D) - at(rho * u[a], unit(D, a, -1), D)) / 2.0
+                        for a in range(D))
+        u_grad_p = sum(u[a] * (at(p_cs2, unit(D, a, 1), D) - at(p_cs2, unit(D, a, -1), D)) / 2.0
+                       for a in range(D))
+        dgdt = -ddiv_rhou + u_grad_p + prm.gamma * p_cs2 * div
+    else:
+        dgdt = g_now - st.H1
+    aC = np.zeros((D, D) + rho.shape)
+    if prm.with_aC:
+        for a in range(D):
+            m = rho * u[a] ** 3
+            aC[a, a] = -(at(m, unit(D, a, 1), D) - at(m, unit(D, a, -1), D)) / 2.0
+    fu_uf = fib[:, None] * u[None, :] + fib[None, :] * u[:, None]
+    aF = (2.0 / D) * eye * rho * cs2 * div - eye * cs2 * dgdt + aC + fu_uf
+
+    F = force_populations(lat, fib, aF)
+    feq = equilibrium(lat, rho, u, theta)
+
+    # Eq. (A.7): hybrid recursive regularisation of Pi^(2).
+    if prm.tau_theta:
+        taubar = prm.mu / (rho * cs2 * theta) + 0.5
+        fd_coef = rho * cs2 * theta * taubar
+    else:
+        taubar = prm.mu / (rho * cs2) + 0.5              # tau = nu / cs^2, Eq. (6)
+        fd_coef = rho * cs2 * taubar
+    strain = du + du.transpose((1, 0) + tuple(range(2, du.ndim))) - (2.0 / D) * eye * div
+    Pi = (prm.sigma * (deviatoric_second_moment(lat, st.f - feq) + 0.5 * st.H2)
+          - (1.0 - prm.sigma) * fd_coef * strain)
+    fneq = regularized_neq(lat, Pi, u)
+    fcol = feq + (1.0 - 1.0 / taubar) * fneq + 0.5 * F    # Eq. (6)
+    H2_new = deviatoric_second_moment(lat, F)
+    return dict(rho=rho, j=j, ustar=ustar, u=u, T=T, fcol=fcol, F=F, aF=aF, feq=feq, Pi=Pi,
+                taubar=taubar, H1_new=g_now, H2_new=H2_new)
+
+
+# ----------------------------------------------------------------------------- fluxes
+
+def lb_face_fluxes(lat, fcol):
+    """LB-consistent fluxes through the face x + e_a/2, Eqs. (A.11)-(A.13).
+
+    Each population crossing the face during streaming counts once; a population
+    that also moves transversally is split half/half between the face in its
+    source column and the face in its destination column:
+      F^rho_a(x) = sum_{c_ia=+1} 1/2 [f_i(x) + f_i(x + e_a - c_i)]
+                 - sum_{c_ia=-1} 1/2 [f_i(x + e_a) + f_i(x - c_i)]
+    Momentum fluxes replace f_i by c_ib f_i. Returns Frho (D, *grid) and
+    Fmom (D, D, *grid) with Fmom[a, b] the flux of rho u_b through the a-face.
+    """
+    D = lat.D
+    cf = lat.c.astype(np.float64)
+    grid = fcol.shape[1:]
+    Frho = np.zeros((D,) + grid)
+    Fmom = np.zeros((D, D) + grid)
+    for a in range(D):
+        for i in range(lat.Q):
+            ci = lat.c[i]
+            if ci[a] == 1:
+                part = 0.5 * (fcol[i] + at(fcol[i], unit(D, a, 1) - ci, D))
+            elif ci[a] == -1:
+                part = -0.5 * (at(fcol[i], unit(D, a, 1), D) + at(fcol[i], -ci, D))
+            else:
+                continue
+            Frho[a] += part
+            for b in range(D):
+                Fmom[a, b] += cf[i, b] * part
+    return Frho, Fmom
+
+
+def muscl_face(phi, ua, a, D):
+    """Eq. (A.14)-(A.16): the MUSCL-Hancock value F*(phi) on the face x + e_a/2.
+
+    The upwind side is chosen by u~ = (u_a(x) + u_a(x + e_a))/2 >= 0. The
+    slope uses eta = (2 u_a - sign(u_a))/3 of the cell itself; no limiter.
+    """
+    e = unit(D, a, 1)
+    m = unit(D, a, -1)
+
+    def slope(p, u):
+        eta = (2.0 * u - np.sign(u)) / 3.0
+        return 0.5 * ((1.0 + eta) * (p - at(p, m, D)) + (1.0 - eta) * (at(p, e, D) - p))
+
+    ua_b = at(ua, e, D)
+    phi_b = at(phi, e, D)
+    left = phi + 0.5 * slope(phi, ua) * (1.0 - ua)           # Phi-bar_{+a/2}(x)
+    right = phi_b - 0.5 * at(slope(phi, ua), e, D) * (1.0 + ua_b)   # Phi-bar_{-a/2}(x + e_a)
+    utilde = 0.5 * (ua + ua_b)
+    return np.where(utilde >= 0.0, left, right)
+
+
+def energy_face_fluxes(lat, prm, rho, u, T, Frho, Fmom):
+    """Eq. (11): total-energy flux through every face x + e_a/2.
+
+    Cell values: p = rho R T, k = |u|^2/2, h = gamma R T/(gamma - 1),
+    H = k + Cv T + p/rho. (h - k) and u_b on the face are the means of the two
+    cells sharing it. Conduction is -lambda (T(x + e_a) - T(x)).
+    """
+    D = lat.D
+    p = rho * prm.R * T
+    k = 0.5 * (u * u).sum(axis=0)
+    h = prm.Cp * T
+    H = k + prm.Cv * T + p / rho
+    FE = np.zeros((D,) + rho.shape)
+    for a in range(D):
+        e = unit(D, a, 1)
+        ua = u[a]
+        hk_f = 0.5 * ((h - k) + at(h - k, e, D))
+        flux = muscl_face(rho * H * ua, ua, a, D)
+        flux = flux + hk_f * (Frho[a] - muscl_face(rho * ua, ua, a, D))
+        for b in range(D):
+            ub_f = 0.5 * (u[b] + at(u[b], e, D))
+            phi = rho * ua * u[b] + (p if a == b else 0.0)
+            flux = flux + ub_f * (Fmom[a, b] - muscl_face(phi, ua, a, D))
+        flux = flux - prm.lam * (at(T, e, D) - T)
+        FE[a] = flux
+    return FE
+
+
+# ----------------------------------------------------------------------------- the step
+
+def stream(lat, fcol):
+    """Pull streaming of Eq. (6): f_i(x, t+1) = f^col_i(x - c_i, t)."""
+    D = lat.D
+    return np.stack([at(fcol[i], -lat.c[i], D) for i in range(lat.Q)])
+
+
+def freestream_state(lat, prm, grid):
+    """Uniform equilibrium at (rho_inf, u_inf, T_inf), zero history derivative."""
+    D = lat.D
+    rho = np.full(grid, prm.rho_inf)
+    u = np.stack([np.full(grid, prm.u_inf[a]) for a in range(D)])
+    T = np.full(grid, prm.T_inf)
+    f = equilibrium(lat, rho, u, T)
+    rhoE = rho * (0.5 * (u * u).sum(axis=0) + prm.Cv * T)
+    return State(f=f, rhoE=rhoE, H1=rho * (1.0 - T), H2=np.zeros((D, D) + grid))
+
+
+def state_from_fields(lat, prm, rho, u, T):
+    """Equilibrium state for given fields; history set so that d/dt rho(1-theta) = 0 at the first step."""
+    D = lat.D
+    f = equilibrium(lat, rho, u, T)
+    rhoE = rho * (0.5 * (u * u).sum(axis=0) + prm.Cv * T)
+    return State(f=f, rhoE=rhoE, H1=rho * (1.0 - T), H2=np.zeros((D, D) + rho.shape))
+
+
+def apply_closure(lat, prm, st):
+    """Inflow/outflow closure along x (reading of the paper's inlet/outlet set-up).
+
+    Columns x = 0, 1 are reset to the free-stream equilibrium (f, rho E, history);
+    columns x = nx-2, nx-1 copy column nx-3 (zero gradient). y and z stay periodic.
+    """
+    if prm.bc != 'inflow_outflow':
+        return st
+    D = lat.D
+    grid = st.rhoE.shape
+    fs = freestream_state(lat, prm, grid[:-1] + (1,))
+    for x in (0, 1):
+        st.f[..., x] = fs.f[..., 0]
+        st.rhoE[..., x] = fs.rhoE[..., 0]
+        st.H1[..., x] = fs.H1[..., 0]
+        st.H2[..., x] = 0.0
+    nx = grid[-1]
+    for x in (nx - 2, nx - 1):
+        st.f[..., x] = st.f[..., nx - 3]
+        st.rhoE[..., x] = st.rhoE[..., nx - 3]
+        st.H1[..., x] = st.H1[..., nx - 3]
+        st.H2[..., x] = st.H2[..., nx - 3]
+    return st
+
+
+def lbm_step(lat, prm, st, fib=None, fE=None, return_diag=False):
+    """Step 5 of Sec. 2.5: solve Eq. (6) and Eq. (10) with the IB forcing terms.
+
+    fib: (D, *grid) momentum forcing; fE: (*grid) energy forcing w + q.
+    Returns the new State (and the collision diagnostics if asked).
+    """
+    D = lat.D
+    grid = st.rhoE.shape
+    if fib is None:
+        fib = np.zeros((D,) + grid)
+    if fE is None:
+        fE = np.zeros(grid)
+    col = collide(lat, prm, st, fib)
+    Frho, Fmom = lb_face_fluxes(lat, col['fcol'])
+    FE = energy_face_fluxes(lat, prm, col['rho'], col['u'], col['T'], Frho, Fmom)
+    # Eq. (10) with the operators of Eq. (A.10): backward differences of the face fluxes.
+    div = sum(FE[a] - at(FE[a], unit(D, a, -1), D) for a in range(D))
+    rhoE_new = st.rhoE - div + fE
+    new = State(f=stream(lat, col['fcol']), rhoE=rhoE_new, H1=col['H1_new'], H2=col['H2_new'],
+                step=st.step + 1)
+    new = apply_closure(lat, prm, new)
+    if return_diag:
+        col.update(Frho=Frho, Fmom=Fmom, FE=FE)
+        return new, col
+    return new
+
+
+def fields(lat, prm, st):
+    """Output fields of a state: rho, force-free u, T from rho E, p = rho R T."""
+    rho, j, u, T = predicted_macros(lat, prm, st.f, st.rhoE)
+    return rho, u, T, rho * prm.R * T
+
+
+__all__ = ['Params', 'State', 'equilibrium', 'regularized_neq', 'force_populations', 'collide',
+           'lb_face_fluxes', 'muscl_face', 'energy_face_fluxes', 'stream', 'lbm_step',
+           'freestream_state', 'state_from_fields', 'apply_closure', 'predicted_macros', 'fields',
+           'deviatoric_second_moment', 'central_gradient', 'at', 'unit']

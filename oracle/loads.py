@@ -1,0 +1,64 @@
+"""Wall loads, boundary-condition errors and the steady-state residual, FP64.
+
+Test infrastructure only (see oracle/__init__.py).
+
+The paper reports drag and lift coefficients (Tables 4, 6-8) without stating how
+the force is integrated; with the IB the fluid feels sum_i f^IB_i, which equals
+sum_l F_l W_l exactly because phi_l sum_{Omega'} delta_il = 1 (Eqs. (15)-(16)).
+The body force is its negative. The heat the IB injects per step, sum_l Q_l W_l,
+gives a Nusselt number. Boundary errors follow Eqs. (35), (36) and (38) with the
+"s" values interpolated two-sidedly (Eq. (12), d = 2) from the updated fields.
+"""
+import numpy as np
+
+from .ib import D_N, T_DIRICHLET, T_NEUMANN, two_sided_interp_lists
+from .lbm import predicted_macros
+
+
+def body_loads(geom, mf):
+    """F_body = -sum_l F_l W_l and Q_heat = sum_l Q_l W_l, in marker order."""
+    act = geom.active
+    Fb = -(mf['F'][act] * geom.W[act, None]).sum(axis=0)
+    Qh = (mf['Qib'][act] * geom.W[act]).sum()
+    return Fb, Qh
+
+
+def coefficients(Fb, Qh, rho_inf, u_ref, ref_len, ref_area, surface, lam, T_wall, T_inf):
+    """Cd, Cl from F/(rho u^2 A / 2); Nu = Q D / (lambda (T_w - T_inf) S)."""
+    q = 0.5 * rho_inf * u_ref * u_ref * ref_area
+    Cd = Fb[0] / q
+    Cl = Fb[1] / q
+    Nu = Qh * ref_len / (lam * (T_wall - T_inf) * surface) if T_wall != T_inf else 0.0
+    return Cd, Cl, Nu
+
+
+def bc_errors(lat, prm, geom, mk, st, u_ref, T_inf, ref_len):
+    """Mean Dirichlet, Neumann and isothermal errors over active markers, Eqs. (35), (36), (38)."""
+    D = lat.D
+    rho, j, u, T = predicted_macros(lat, prm, st.f, st.rhoE)
+    uf = u.reshape(D, -1)
+    Tf = T.reshape(-1)
+    lins, ws = two_sided_interp_lists(geom.dims, geom.X, 2.0)
+    plins, pws = two_sided_interp_lists(geom.dims, geom.P, 1.0)
+    e_dir, e_neu, e_iso = [], [], []
+    for l in range(len(geom.X)):
+        if not geom.active[l]:
+            continue
+        us = (uf[:, lins[l]] * ws[l]).sum(axis=1)
+        Ts = (Tf[lins[l]] * ws[l]).sum()
+        e_dir.append(np.sqrt(((us - mk.u_wall[l]) ** 2).sum()) / u_ref)
+        if mk.t_kind[l] == T_DIRICHLET:
+            e_iso.append(abs(Ts - mk.t_value[l]) / mk.t_value[l])
+        elif mk.t_kind[l] == T_NEUMANN:
+            TPs = (Tf[plins[l]] * pws[l]).sum()
+            e_neu.append(abs((TPs - Ts) / D_N - mk.t_value[l]) / (T_inf / ref_len))
+    mean = lambda v: float(np.mean(v)) if v else 0.0
+    return mean(e_dir), mean(e_neu), mean(e_iso)
+
+
+def residual(lat, prm, st_old, st_new, u_ref):
+    """r = ||u^{n+1} - u^n||_2 / (u_ref sqrt(N)) over all nodes, force-free velocities."""
+    _, _, u0, _ = predicted_macros(lat, prm, st_old.f, st_old.rhoE)
+    _, _, u1, _ = predicted_macros(lat, prm, st_new.f, st_new.rhoE)
+    N = st_new.rhoE.size
+    return float(np.sqrt(((u1 - u0) ** 2).sum()) / (u_ref * np.sqrt(N)))

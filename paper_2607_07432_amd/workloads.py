@@ -1,0 +1,239 @@
+"""Seeded synthetic inputs: marker geometries and flow parameters of the benchmark workloads.
+
+This module holds input generation only (body shapes, marker placement, the
+conversion of Mach/Reynolds numbers to lattice units, seeds). It contains none
+of the time step's arithmetic. Both the HIP path and the CPU checker are fed
+from it.
+
+Lattice units: dx = dt = 1, R = c_s^2 = 1/3, temperatures in units of T_ref.
+The paper fixes Delta x / Delta s = 1 (markers about one cell apart, Sec. 2.4),
+gamma = 1.4 (Sec. 3.4); the Prandtl number is not given and is taken as 0.71.
+"""
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+R_GAS = 1.0 / 3.0
+GAMMA = 1.4
+PRANDTL = 0.71
+
+METHOD_DIBM, METHOD_FODIBM, METHOD_FODIBM_R = 0, 1, 2
+KERNEL_COS, KERNEL_ROMA3 = 0, 1
+T_NONE, T_DIRICHLET, T_NEUMANN = 0, 1, 2
+
+
+def cylinder_markers(center, radius, m):
+    """X_l = c + R (cos 2 pi l/m, sin 2 pi l/m) with outward normals."""
+    t = 2.0 * np.pi * np.arange(m) / m
+    n = np.stack([np.cos(t), np.sin(t)], axis=1)
+    return np.asarray(center, dtype=np.float64)[None, :] + radius * n, n
+
+
+def sphere_markers(center, radius, m):
+    """Fibonacci lattice on the sphere: z_l = 1 - (2l+1)/m, azimuth l * golden angle."""
+    l = np.arange(m, dtype=np.float64)
+    z = 1.0 - (2.0 * l + 1.0) / m
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    ga = np.pi * (3.0 - np.sqrt(5.0))
+    phi = ga * l
+    n = np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
+    return np.asarray(center, dtype=np.float64)[None, :] + radius * n, n
+
+
+def ellipse_markers(center, a, b, angle, m, dense=20000):
+    """m markers at equal arc length on an ellipse (semi-axes a, b, rotated by angle)."""
+    t = np.linspace(0.0, 2.0 * np.pi, dense + 1)
+    px, py = a * np.cos(t), b * np.sin(t)
+    seg = np.hypot(np.diff(px), np.diff(py))
+    s = np.concatenate([[0.0], np.cumsum(seg)])
+    target = s[-1] * np.arange(m) / m
+    tm = np.interp(target, s, t)
+    x, y = a * np.cos(tm), b * np.sin(tm)
+    nx_, ny_ = b * np.cos(tm), a * np.sin(tm)          # outward normal of the unrotated ellipse
+    nn = np.hypot(nx_, ny_)
+    nx_, ny_ = nx_ / nn, ny_ / nn
+    ca, sa = math.cos(angle), math.sin(angle)
+    X = np.stack([center[0] + ca * x - sa * y, center[1] + sa * x + ca * y], axis=1)
+    n = np.stack([ca * nx_ - sa * ny_, sa * nx_ + ca * ny_], axis=1)
+    return X, n
+
+
+def ellipse_perimeter(a, b, dense=20000):
+    t = np.linspace(0.0, 2.0 * np.pi, dense + 1)
+    return float(np.hypot(np.diff(a * np.cos(t)), np.diff(b * np.sin(t))).sum())
+
+
+def star_markers(center, r0, dr, m):
+    """Five-point star of Eq. (39): r = r0 + dr cos(5 t), normals from the tangent."""
+    t = 2.0 * np.pi * np.arange(m) / m
+    r = r0 + dr * np.cos(5 * t)
+    drdt = -5 * dr * np.sin(5 * t)
+    x, y = r * np.cos(t), r * np.sin(t)
+    tx, ty = drdt * np.cos(t) - r * np.sin(t), drdt * np.sin(t) + r * np.cos(t)
+    nn = np.hypot(tx, ty)
+    n = np.stack([ty / nn, -tx / nn], axis=1)
+    return np.stack([center[0] + x, center[1] + y], axis=1), n
+
+
+def flow_units(mach, reynolds, ref_len, T_inf, rho_inf=1.0, gamma=GAMMA, prandtl=PRANDTL):
+    """Free-stream speed, viscosity and conductivity in lattice units.
+
+    u = Ma sqrt(gamma R T_inf); mu = rho u L / Re; lambda = mu Cp / Pr.
+    """
+    u = mach * math.sqrt(gamma * R_GAS * T_inf)
+    mu = rho_inf * u * ref_len / reynolds
+    cp = gamma * R_GAS / (gamma - 1.0)
+    return u, mu, mu * cp / prandtl
+
+
+def reference_temperatures(T_wall_ratio):
+    """T_ref = (T_inf + T_w)/2 (temperatures in units of T_ref): returns (T_inf, T_w)."""
+    t_inf = 2.0 / (1.0 + T_wall_ratio)
+    return t_inf, T_wall_ratio * t_inf
+
+
+@dataclass
+class Case:
+    """One flow problem: grid, gas, free stream and the immersed body."""
+    name: str
+    dim: int
+    dims: tuple
+    mu: float
+    lam: float
+    u_inf: tuple
+    T_inf: float
+    rho_inf: float = 1.0
+    gamma: float = GAMMA
+    sigma: float = 0.98
+    bc: str = 'inflow_outflow'
+    X: np.ndarray = None
+    n: np.ndarray = None
+    u_wall: np.ndarray = None
+    t_kind: np.ndarray = None
+    t_value: np.ndarray = None
+    method: int = METHOD_FODIBM_R
+    kernel: int = KERNEL_COS
+    ref_len: float = 1.0
+    ref_area: float = 1.0
+    surface: float = 1.0
+    T_wall: float = 1.0
+    steps: int = 1
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self):
+        return int(np.prod(self.dims))
+
+    @property
+    def u_ref(self):
+        return float(np.linalg.norm(self.u_inf))
+
+
+def _markers_common(X, n, t_kind, t_value):
+    m = len(X)
+    return dict(X=X, n=n, u_wall=np.zeros_like(X), t_kind=np.full(m, t_kind, dtype=np.int32),
+                t_value=np.full(m, t_value, dtype=np.float64))
+
+
+def cylinder_case(nx=200, ny=100, center=(60.0, 50.0), diameter=20.0, markers=63, mach=0.2,
+                  reynolds=40.0, T_wall_ratio=1.2, method=METHOD_FODIBM_R, kernel=KERNEL_COS, steps=1000):
+    """2D cylinder, no-slip, isothermal wall: D2Q9, 200 x 100, D = 20 at (60, 50), 63 markers."""
+    T_inf, T_w = reference_temperatures(T_wall_ratio)
+    u, mu, lam = flow_units(mach, reynolds, diameter, T_inf)
+    X, n = cylinder_markers(center, diameter / 2.0, markers)
+    return Case(name='cylinder2d', dim=2, dims=(nx, ny), mu=mu, lam=lam, u_inf=(u, 0.0), T_inf=T_inf,
+                method=method, kernel=kernel, ref_len=diameter, ref_area=diameter,
+                surface=math.pi * diameter, T_wall=T_w, steps=steps,
+                **_markers_common(X, n, T_DIRICHLET, T_w))
+
+
+def sphere_case(nx=384, ny=192, nz=192, diameter=32.0, center=None, mach=0.3, reynolds=100.0,
+                T_wall_ratio=None, method=METHOD_FODIBM_R, steps=5000, markers=None):
+    """3D sphere: adiabatic (T_wall_ratio None, theta_inf = 1) or isothermal wall."""
+    if center is None:
+        center = (0.3 * nx, ny / 2.0, nz / 2.0)
+    if T_wall_ratio is None:
+        T_inf, T_w, kind, tv = 1.0, 1.0, T_NEUMANN, 0.0
+    else:
+        T_inf, T_w = reference_temperatures(T_wall_ratio)
+        kind, tv = T_DIRICHLET, T_w
+    u, mu, lam = flow_units(mach, reynolds, diameter, T_inf)
+    m = markers if markers is not None else int(round(math.pi * diameter * diameter))
+    X, n = sphere_markers(center, diameter / 2.0, m)
+    return Case(name='sphere3d', dim=3, dims=(nx, ny, nz), mu=mu, lam=lam, u_inf=(u, 0.0, 0.0),
+                T_inf=T_inf, method=method, ref_len=diameter, ref_area=math.pi * diameter ** 2 / 4,
+                surface=math.pi * diameter ** 2, T_wall=T_w, steps=steps,
+                **_markers_common(X, n, kind, tv))
+
+
+def config1(**kw):
+    """200 x 100 D2Q9 cylinder D = 20 at (60, 50), 63 markers, Ma 0.2, Re 40, T_w = 1.2 T_inf."""
+    return cylinder_case(**kw)
+
+
+def config2(reynolds=100.0, **kw):
+    """384 x 192 x 192 D3Q19, sphere D = 32, 3217 markers, adiabatic, Ma 0.3, Re 100-300."""
+    return sphere_case(reynolds=reynolds, **kw)
+
+
+def config3(**kw):
+    """512 x 256 x 256 D3Q19, sphere D = 32, isothermal T_w = 1.5 T_inf, Ma 0.5, Re 300."""
+    kw.setdefault('nx', 512)
+    kw.setdefault('ny', 256)
+    kw.setdefault('nz', 256)
+    return sphere_case(mach=0.5, reynolds=300.0, T_wall_ratio=1.5, **kw)
+
+
+def batched_cases(count=64, seed0=1000, steps=2000):
+    """Uneven 2D ellipse cases: M ~ U{64..256}, nx = 4M, ny = nx/2, aspect U[1,4], angle U[0,90 deg],
+    Ma U[0.1,0.5], Re U[20,200] on L = 2a, isothermal T_w U[1,1.5] T_inf."""
+    cases = []
+    for s in range(count):
+        rng = np.random.Generator(np.random.PCG64(seed0 + s))
+        m = int(rng.integers(64, 257))
+        aspect = rng.uniform(1.0, 4.0)
+        angle = math.radians(rng.uniform(0.0, 90.0))
+        mach = rng.uniform(0.1, 0.5)
+        re = rng.uniform(20.0, 200.0)
+        tw = rng.uniform(1.0, 1.5)
+        cases.append(ellipse_case(m, aspect, angle, mach, re, tw, steps=steps, name=f'batch{s}'))
+    return cases
+
+
+def ellipse_case(m, aspect, angle, mach, reynolds, T_wall_ratio, steps=2000, name='ellipse',
+                 nx=None, ny=None):
+    """Ellipse of perimeter m dx (one marker per cell), centre (0.3 nx, 0.5 ny)."""
+    nx = nx if nx is not None else 4 * m
+    ny = ny if ny is not None else nx // 2
+    # perimeter(a, a/aspect) = m  ->  scale a unit-major ellipse
+    per1 = ellipse_perimeter(1.0, 1.0 / aspect)
+    a = m / per1
+    b = a / aspect
+    T_inf, T_w = reference_temperatures(T_wall_ratio)
+    u, mu, lam = flow_units(mach, reynolds, 2.0 * a, T_inf)
+    X, n = ellipse_markers((0.3 * nx, 0.5 * ny), a, b, angle, m)
+    kind = T_DIRICHLET if T_wall_ratio != 1.0 else T_DIRICHLET
+    return Case(name=name, dim=2, dims=(nx, ny), mu=mu, lam=lam, u_inf=(u, 0.0), T_inf=T_inf,
+                ref_len=2.0 * a, ref_area=2.0 * a, surface=m, T_wall=T_w, steps=steps,
+                extra=dict(a=a, b=b, angle=angle, mach=mach, reynolds=reynolds),
+                **_markers_common(X, n, kind, T_w))
+
+
+def random_state_perturbation(case, seed, amp_rho=1e-3, amp_u=None, amp_T=1e-3):
+    """Smooth seeded perturbation fields (rho, u, T) around the free stream, for parity tests."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    grid = tuple(case.dims[::-1])
+    D = case.dim
+    amp_u = amp_u if amp_u is not None else 0.05 * max(case.u_ref, 0.01)
+
+    def smooth():
+        a = rng.standard_normal(grid)
+        for ax in range(D):
+            a = (np.roll(a, 1, ax) + 2 * a + np.roll(a, -1, ax)) / 4.0
+        return a / max(np.abs(a).max(), 1e-300)
+
+    rho = case.rho_inf * (1.0 + amp_rho * smooth())
+    u = np.stack([case.u_inf[a] + amp_u * smooth() for a in range(D)])
+    T = case.T_inf * (1.0 + amp_T * smooth())
+    return rho, u, T

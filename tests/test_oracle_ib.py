@@ -1,0 +1,223 @@
+"""Pins of the oracle's immersed-boundary geometry and operators (Secs. 2.3-2.4).
+
+Closed forms derived from Eqs. (16), (17), (19), (25), (27); a brute-force
+re-derivation of the index lists over every node of tiny grids; exact identities
+of the interpolation/spreading pair.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import ib
+
+GOLD = os.path.join(os.path.dirname(__file__), 'golden')
+
+
+def test_cos_kernel_tabulated_values():
+    r = np.array([0.0, 0.5, 1.0, 1.5, 2.0, -0.5, -1.5])
+    v = ib.cos_kernel(r, 2.0)
+    exp = [0.5, (2 + math.sqrt(2)) / 8, 0.25, (2 - math.sqrt(2)) / 8, 0.0, (2 + math.sqrt(2)) / 8,
+           (2 - math.sqrt(2)) / 8]
+    assert np.allclose(v, exp, rtol=0, atol=1e-16)
+    assert np.allclose(ib.cos_kernel([0.0, 0.5, 1.0], 1.0), [1.0, 0.5, 0.0], rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize('d', [1.0, 2.0])
+def test_cos_kernel_partition_of_unity_and_first_moment(d):
+    for r in np.linspace(0.0, 0.999, 37):
+        nodes = np.arange(-3, 5)
+        off = nodes - r
+        w = ib.cos_kernel(off, d) * (np.abs(off) < d)
+        assert abs(w.sum() - 1.0) < 1e-15
+        m1 = (w * off).sum()
+        closed = (0.5 - r + (math.sin(math.pi * r / 2) - math.cos(math.pi * r / 2)) / 2 if d == 2.0
+                  else 0.5 - r - math.cos(math.pi * r) / 2)
+        assert abs(m1 - closed) < 1e-15
+
+
+def test_cos_kernel_first_moment_extremes():
+    rs = np.linspace(0, 1, 200001)
+    m2 = 0.5 - rs + (np.sin(np.pi * rs / 2) - np.cos(np.pi * rs / 2)) / 2
+    assert abs(np.abs(m2).max() - 0.0210880) < 2e-6
+    m1 = 0.5 - rs - np.cos(np.pi * rs) / 2
+    assert abs(np.abs(m1).max() - 0.1052568) < 2e-6
+
+
+def test_roma3_partition_and_first_moment():
+    for r in np.linspace(0.0, 0.999, 41):
+        off = np.arange(-3, 5) - r
+        w = ib.roma3_kernel(off)
+        assert abs(w.sum() - 1.0) < 1e-14
+        assert abs((w * off).sum()) < 1e-14
+
+
+def _fraction(s):
+    if s == 'nan':
+        return None
+    if 'sqrt' in s:
+        return eval(s.replace('sqrt', 'math.sqrt'))
+    return float(Fraction(s))
+
+
+def load_flat_wall():
+    rows = []
+    with open(os.path.join(GOLD, 'ib_flat_wall.txt')) as fh:
+        for line in fh:
+            if line.startswith('#') or not line.strip():
+                continue
+            name, method, off, phi, dbv, W, ratio = line.split()
+            rows.append((name, method, float(off), _fraction(phi), _fraction(dbv), _fraction(W), _fraction(ratio)))
+    return rows
+
+
+@pytest.mark.parametrize('case', load_flat_wall(), ids=lambda c: c[0])
+def test_flat_wall_worked_values(case):
+    name, method, off, phi, dbv, W, ratio = case
+    nx, ny, y0 = 40, 16, 8.0
+    X = np.array([[float(x), y0 + off] for x in range(4, nx - 4)])
+    n = np.tile([0.0, 1.0], (len(X), 1))
+    m = ib.FODIBM_R if method == 'FODIBM' else ib.DIBM
+    g = ib.build_geometry((nx, ny), X, n, m)
+    mid = [l for l in range(len(X)) if 12 <= X[l, 0] <= nx - 13]   # away from the wall's ends
+    assert np.allclose(g.phi[mid], phi, rtol=0, atol=1e-14)
+    assert np.allclose(g.dBV[mid], dbv, rtol=0, atol=1e-14)
+    assert np.allclose(g.W[mid], W, rtol=0, atol=1e-13)
+    if ratio is not None:
+        # no-slip reconstruction factor of Eq. (27): u^Vt / u^P* = -d_BV / d_PB
+        assert np.allclose(-g.dBV[mid] / ib.D_N, ratio, rtol=0, atol=1e-14)
+
+
+def test_linear_profile_reconstruction_exact():
+    # u = a * s (s = signed distance from a straight wall on a node row): the projection point
+    # sits half-way between rows, where the d = 1 kernel has zero first moment, so u^P* = 1.5 a
+    # exactly and Eq. (27) returns -a d_BV, the linear profile's value at V.
+    nx, ny, y0, a = 40, 16, 8.0, 0.37
+    X = np.array([[float(x), y0] for x in range(4, nx - 4)])
+    n = np.tile([0.0, 1.0], (len(X), 1))
+    g = ib.build_geometry((nx, ny), X, n, ib.FODIBM_R)
+    ys = np.repeat(np.arange(ny), nx).astype(float)
+    u = np.stack([a * (ys - y0), np.zeros(nx * ny)])
+    mk = ib.Markers(u_wall=np.zeros_like(X), t_kind=np.zeros(len(X), int), t_value=np.zeros(len(X)))
+    rho = np.ones(nx * ny)
+    T = np.ones(nx * ny)
+    mf = ib.marker_forces(g, mk, _Prm(), rho, rho * u, u, T)
+    mid = [l for l in range(len(X)) if 12 <= X[l, 0] <= nx - 13]
+    assert np.allclose(mf['uP'][mid, 0], 1.5 * a, rtol=0, atol=1e-14)
+    assert np.allclose(mf['ut'][mid, 0], -a * g.dBV[mid], rtol=0, atol=1e-14)
+
+
+class _Prm:
+    Cv = 5.0 / 6.0
+
+
+def brute_geometry(dims, X, n, one_sided=True):
+    """Independent re-derivation over every node of the grid (pure Python loops)."""
+    D = len(dims)
+    M = len(X)
+    nodes = [tuple(p) for p in np.ndindex(*dims[::-1])]
+    nodes = [p[::-1] for p in nodes]
+    supp = {l: [] for l in range(M)}
+    for p in nodes:
+        inside = None
+        for l in range(M):
+            if all(abs(float(p[a]) - X[l][a]) < 2.0 for a in range(D)):
+                if inside is None and one_sided:
+                    best, bestd = 0, None
+                    for k in range(M):
+                        dd = 0.0
+                        for a in range(D):
+                            dd = dd + (float(p[a]) - X[k][a]) * (float(p[a]) - X[k][a])
+                        if bestd is None or dd < bestd:
+                            best, bestd = k, dd
+                    dot = 0.0
+                    for a in range(D):
+                        dot = dot + (float(p[a]) - X[best][a]) * n[best][a]
+                    inside = dot <= 0.0
+                if (not one_sided) or inside:
+                    lin = 0
+                    for a in range(D - 1, -1, -1):
+                        lin = lin * dims[a] + p[a]
+                    supp[l].append(lin)
+    return {l: sorted(v) for l, v in supp.items()}
+
+
+@pytest.mark.parametrize('D', [2, 3])
+def test_lists_match_brute_force(D):
+    rng = np.random.default_rng(7 + D)
+    if D == 2:
+        dims = (24, 20)
+        t = np.linspace(0, 2 * np.pi, 17, endpoint=False) + 0.1
+        c, R = np.array([11.3, 9.7]), 4.6
+        nrm = np.stack([np.cos(t), np.sin(t)], 1)
+    else:
+        dims = (14, 13, 12)
+        m = 40
+        z = 1 - (2 * np.arange(m) + 1) / m
+        ph = np.arange(m) * np.pi * (3 - np.sqrt(5))
+        nrm = np.stack([np.sqrt(1 - z * z) * np.cos(ph), np.sqrt(1 - z * z) * np.sin(ph), z], 1)
+        c, R = np.array([6.6, 6.2, 5.9]), 2.9
+    X = c + R * nrm + 0.01 * rng.standard_normal(nrm.shape)
+    for method, one_sided in ((ib.FODIBM_R, True), (ib.DIBM, False)):
+        g = ib.build_geometry(dims, X, nrm, method)
+        bf = brute_geometry(dims, X.tolist(), nrm.tolist(), one_sided)
+        for l in range(len(X)):
+            assert sorted(g.supp_lin[l].tolist()) == bf[l]
+
+
+def test_cylinder_interior_equals_closed_disk():
+    # The 63-marker cylinder D = 20 at (60, 50): nearest-marker interior test equals |x - c| <= R.
+    t = 2 * np.pi * np.arange(63) / 63
+    nrm = np.stack([np.cos(t), np.sin(t)], 1)
+    X = np.array([60.0, 50.0]) + 10.0 * nrm
+    g = ib.build_geometry((200, 100), X, nrm, ib.FODIBM_R)
+    cand = np.unique(np.concatenate([ib.linear_index(ib.box_nodes(x, 2.0), (200, 100)) for x in X]))
+    xs, ys = cand % 200, cand // 200
+    disk = (xs - 60) ** 2 + (ys - 50) ** 2 <= 100
+    assert set(g.interior_lin.tolist()) == set(cand[disk].tolist())
+    assert int(((xs - 60) ** 2 + (ys - 50) ** 2 == 100).sum()) == 12
+
+
+def _ring_geometry(method=ib.FODIBM_R):
+    t = 2 * np.pi * np.arange(40) / 40
+    nrm = np.stack([np.cos(t), np.sin(t)], 1)
+    X = np.array([20.3, 19.6]) + 6.4 * nrm
+    return ib.build_geometry((40, 40), X, nrm, method), X
+
+
+@pytest.mark.parametrize('method', [ib.FODIBM_R, ib.DIBM])
+def test_spread_conserves_total_force(method):
+    # sum_i g_i = sum_l G_l W_l because phi_l sum_{i in S'_l} delta_il = 1 (Eqs. (15), (16)).
+    g, X = _ring_geometry(method)
+    rng = np.random.default_rng(0)
+    F = rng.standard_normal((len(X), 2))
+    G = rng.standard_normal(len(X))
+    fib, fE = ib.spread(g, F, G)
+    assert np.allclose(fib.sum(0), (F * g.W[:, None]).sum(0), rtol=1e-13, atol=1e-13)
+    assert abs(fE.sum() - (G * g.W).sum()) < 1e-12
+
+
+def test_single_marker_reciprocity():
+    # One isolated marker: I[S[G]] = G exactly with the weight of Eq. (17).
+    X = np.array([[10.37, 9.81]])
+    nrm = np.array([[0.6, 0.8]])
+    g = ib.build_geometry((24, 24), X, nrm, ib.FODIBM_R)
+    fib, fE = ib.spread(g, np.array([[1.7, -0.4]]), np.array([2.5]))
+    field = np.zeros((2, 24 * 24))
+    field[:, g.rows] = fib.T
+    interp = g.phi[0] * (field[:, g.supp_lin[0]] * g.supp_w[0]).sum(1)
+    assert np.allclose(interp, [1.7, -0.4], rtol=0, atol=1e-14)
+
+
+def test_interpolating_a_constant_and_X_star():
+    g, X = _ring_geometry()
+    for l in range(len(X)):
+        # phi_l sum delta = 1, so a constant is reproduced exactly (Eqs. (14), (16))
+        assert abs(g.phi[l] * g.supp_w[l].sum() - 1.0) < 1e-14
+        # X* is a convex combination of interior nodes: it lies inside, Eq. (25)
+        assert ((g.Xstar[l] - X[l]) * (X[l] - [20.3, 19.6])).sum() < 0.0
+    gd, _ = _ring_geometry(ib.DIBM)
+    # DIBM: the effective boundary is the marker up to the kernel's first moment
+    assert np.abs(gd.Xstar - X).max() < 0.0211 * 1.000001

@@ -1,0 +1,199 @@
+"""Pins of the oracle's hybrid LBM step (Sec. 2.2, Appendix A).
+
+* the general face-flux rule against the paper's explicit Eqs. (A.11)-(A.13);
+* exact discrete identities (mass, momentum, energy);
+* MUSCL-Hancock exactness on linear data (Eqs. (A.14)-(A.16));
+* analytic flows: shear-wave decay at 2 nu k^2 (theta = 1 and 0.8), sound speed
+  sqrt(gamma theta / 3), isobaric thermal decay lambda k^2 / (rho Cp).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import lattice, lbm
+from oracle.lbm import at, unit
+
+GOLD = os.path.join(os.path.dirname(__file__), 'golden')
+
+
+def rnd_state(lat, grid, seed, amp_u=0.05):
+    rng = np.random.default_rng(seed)
+    D = lat.D
+
+    def smooth(a):
+        for ax in range(D):
+            a = (np.roll(a, 1, ax) + 2 * a + np.roll(a, -1, ax)) / 4
+        return a
+    rho = 1.0 + 0.02 * smooth(rng.standard_normal(grid))
+    u = amp_u * smooth(rng.standard_normal((D,) + grid))
+    T = 0.9 + 0.03 * smooth(rng.standard_normal(grid))
+    st = lbm.state_from_fields(lat, prm_default(), rho, u, T)
+    # non-equilibrium content and history, so every term of the collision is exercised
+    st.f = st.f + 1e-3 * smooth(rng.standard_normal(st.f.shape)) * lat.w.reshape((-1,) + (1,) * D)
+    st.H2 = 1e-4 * rng.standard_normal(st.H2.shape)
+    st.H2 = 0.5 * (st.H2 + st.H2.transpose((1, 0) + tuple(range(2, st.H2.ndim))))
+    st.H2 -= np.eye(D).reshape((D, D) + (1,) * D) * sum(st.H2[a, a] for a in range(D)) / D
+    return st
+
+
+def prm_default(**kw):
+    base = dict(mu=0.03, lam=0.05)
+    base.update(kw)
+    return lbm.Params(**base)
+
+
+def test_general_flux_rule_matches_explicit_d3q19_terms():
+    lat = lattice.d3q19()
+    rng = np.random.default_rng(0)
+    grid = (5, 6, 7)
+    fcol = rng.standard_normal((19,) + grid)
+    Frho, Fmom = lbm.lb_face_fluxes(lat, fcol)
+    explicit = {0: 0.0, 1: 0.0, 2: 0.0}
+    mom = {a: [0.0, 0.0, 0.0] for a in range(3)}
+    with open(os.path.join(GOLD, 'd3q19_face_flux_terms.txt')) as fh:
+        for line in fh:
+            if line.startswith('#') or not line.strip():
+                continue
+            face, coef, i, dx, dy, dz = line.split()
+            a = 'xyz'.index(face)
+            i, coef = int(i), float(coef)
+            term = coef * at(fcol[i], [int(dx), int(dy), int(dz)], 3)
+            explicit[a] = explicit[a] + term
+            for b in range(3):
+                mom[a][b] = mom[a][b] + lat.c[i, b] * term
+    for a in range(3):
+        assert np.abs(Frho[a] - explicit[a]).max() < 1e-14
+        for b in range(3):
+            assert np.abs(Fmom[a, b] - mom[a][b]).max() < 1e-14
+
+
+@pytest.mark.parametrize('D', [2, 3])
+def test_discrete_mass_and_momentum_flux_identities(D):
+    lat = lattice.for_dim(D)
+    grid = (8, 9) if D == 2 else (5, 6, 7)
+    st = rnd_state(lat, grid, 1)
+    rng = np.random.default_rng(2)
+    fib = 1e-3 * rng.standard_normal((D,) + grid)
+    new, dg = lbm.lbm_step(lat, prm_default(), st, fib, None, return_diag=True)
+    cf = lat.c.astype(float)
+    rho_new = new.f.sum(0)
+    rho_col = dg['fcol'].sum(0)
+    div = sum(dg['Frho'][a] - at(dg['Frho'][a], unit(D, a, -1), D) for a in range(D))
+    assert np.abs(rho_col - dg['rho']).max() < 1e-15            # collision conserves mass
+    assert np.abs((rho_new - rho_col) + div).max() < 1e-14       # Eq. (A.10) with (A.11)-(A.13)
+    j_new = np.einsum('ia,i...->a...', cf, new.f)
+    j_col = np.einsum('ia,i...->a...', cf, dg['fcol'])
+    for b in range(D):
+        divb = sum(dg['Fmom'][a, b] - at(dg['Fmom'][a, b], unit(D, a, -1), D) for a in range(D))
+        assert np.abs((j_new[b] - j_col[b]) + divb).max() < 1e-14
+    # collision adds the full momentum impulse: sum c f^col = j + f^IB
+    assert np.abs(j_col - (dg['j'] + fib)).max() < 1e-15
+
+
+@pytest.mark.parametrize('D', [2, 3])
+def test_periodic_conservation_with_forcing(D):
+    lat = lattice.for_dim(D)
+    grid = (10, 12) if D == 2 else (6, 7, 8)
+    st = rnd_state(lat, grid, 3)
+    rng = np.random.default_rng(4)
+    fib = 1e-3 * rng.standard_normal((D,) + grid)
+    fE = 1e-3 * rng.standard_normal(grid)
+    new = lbm.lbm_step(lat, prm_default(), st, fib, fE)
+    cf = lat.c.astype(float)
+    assert abs(new.f.sum() - st.f.sum()) < 1e-11
+    dj = (np.einsum('ia,i...->a...', cf, new.f) - np.einsum('ia,i...->a...', cf, st.f)).reshape(D, -1).sum(1)
+    assert np.allclose(dj, fib.reshape(D, -1).sum(1), rtol=0, atol=1e-12)
+    assert abs(new.rhoE.sum() - st.rhoE.sum() - fE.sum()) < 1e-11
+
+
+def test_muscl_exact_on_linear_data():
+    D = 2
+    for ua in (0.3, -0.2, 0.0):
+        x = np.arange(12, dtype=float)[None, :] * np.ones((3, 1))
+        phi = 1.7 + 0.4 * x
+        u = np.full(x.shape, ua)
+        val = lbm.muscl_face(phi, u, 0, D)
+        interior = val[:, 1:-2]
+        expect = 1.7 + 0.4 * (x[:, 1:-2] + 0.5 - ua / 2)
+        assert np.abs(interior - expect).max() < 1e-14
+
+
+@pytest.mark.parametrize('D', [2, 3])
+def test_freestream_is_a_fixed_point(D):
+    lat = lattice.for_dim(D)
+    prm = prm_default(u_inf=(0.1, 0.02, -0.01)[:D], T_inf=0.9, bc='inflow_outflow')
+    grid = (6, 12) if D == 2 else (4, 5, 12)
+    st = lbm.freestream_state(lat, prm, grid)
+    new = lbm.lbm_step(lat, prm, st)
+    assert np.abs(new.f - st.f).max() < 1e-15
+    assert np.abs(new.rhoE - st.rhoE).max() < 1e-15
+
+
+def shear_wave_rate(D, theta, tau_theta, L=32, mu=0.05, steps=200, U=0.01):
+    lat = lattice.for_dim(D)
+    prm = lbm.Params(mu=mu, lam=mu * (7 / 6) / 0.71, T_inf=theta, tau_theta=tau_theta)
+    grid = (L, L) if D == 2 else (2, L, L)
+    prof = np.sin(2 * np.pi * np.arange(L) / L)
+    shape = (L, 1) if D == 2 else (1, L, 1)
+    u = np.zeros((D,) + grid)
+    u[0] = U * prof.reshape(shape)
+    st = lbm.state_from_fields(lat, prm, np.ones(grid), u, np.full(grid, theta))
+    for _ in range(steps):
+        st = lbm.lbm_step(lat, prm, st)
+    _, uu, _, _ = lbm.fields(lat, prm, st)
+    amp = (uu[0] * prof.reshape(shape)).sum() / (prof ** 2).sum() / (np.prod(grid) / L)
+    k = 2 * np.pi / L
+    return -np.log(amp / U) / steps / (mu * k * k)
+
+
+@pytest.mark.parametrize('D,theta', [(2, 1.0), (2, 0.8), (3, 0.8)])
+def test_shear_wave_decay_literal_tau(D, theta):
+    # tau = nu / cs^2 (Eq. (6)): the viscosity is mu at any theta, to the O(k^2) lattice error.
+    ratio = shear_wave_rate(D, theta, False, steps=200 if D == 2 else 100)
+    assert abs(ratio - 1.0) < 0.02
+
+
+def test_shear_wave_rejects_theta_scaled_tau():
+    # The alternative tau = mu / (rho cs^2 theta) makes the viscosity mu / theta.
+    ratio = shear_wave_rate(2, 0.8, True)
+    assert abs(ratio - 1.25) < 0.03
+
+
+def _wave(D, theta, kind, L=64, mu=0.01, steps=300, A=1e-4):
+    lat = lattice.for_dim(D)
+    lam = mu * (7 / 6) / 0.71
+    prm = lbm.Params(mu=mu, lam=lam, T_inf=theta)
+    grid = (2, L)
+    c = np.cos(2 * np.pi * np.arange(L) / L)
+    if kind == 'acoustic':
+        rho = np.ones(grid) * (1 + A * c)
+        T = theta * (1 + 0.4 * A * c) * np.ones(grid)
+    else:
+        T = theta * (1 + A * c) * np.ones(grid)
+        rho = np.ones(grid) / (1 + A * c)
+    st = lbm.state_from_fields(lat, prm, rho, np.zeros((D,) + grid), T)
+    hist = []
+    for _ in range(steps):
+        st = lbm.lbm_step(lat, prm, st)
+        r, _, TT, _ = lbm.fields(lat, prm, st)
+        hist.append((r[0] * c).sum() / (c * c).sum() if kind == 'acoustic'
+                    else ((TT[0] - theta) * c).sum() / (c * c).sum())
+    return np.array(hist), lam
+
+
+@pytest.mark.parametrize('theta', [1.0, 0.8])
+def test_sound_speed(theta):
+    h, _ = _wave(2, theta, 'acoustic', steps=400)
+    zc = np.where(np.diff(np.sign(h)) != 0)[0]
+    period = 2 * np.mean(np.diff(zc))
+    k = 2 * np.pi / 64
+    assert abs((2 * np.pi / period / k) / np.sqrt(1.4 * theta / 3) - 1.0) < 0.005
+
+
+@pytest.mark.parametrize('theta', [1.0, 0.8])
+def test_thermal_mode_decay(theta):
+    h, lam = _wave(2, theta, 'thermal')
+    rate = -np.log(h[-1] / h[99]) / 200
+    k = 2 * np.pi / 64
+    assert abs(rate / (lam * k * k / (7 / 6)) - 1.0) < 0.03
