@@ -1,0 +1,167 @@
+/*
+ * lbmib.h -- C ABI of the MI355X (gfx950) FODIBM-R + hybrid lattice Boltzmann library.
+ *
+ * One time step (Sec. 2.5 of Mao, Zhao, Boivin, Favier, arXiv 2607.07432):
+ *   1. predicted density, momentum, velocity and temperature at the Lagrangian
+ *      markers by one-sided interpolation over the interior nodes (Eq. (14));
+ *   2. velocity and temperature at the projection points by two-sided
+ *      interpolation with the d = 1 kernel (Eq. (12));
+ *   3. Lagrangian forces with the reconstructed targets (Eqs. (27), (29)-(32))
+ *      or the plain targets (Eqs. (20)-(22));
+ *   4. one-sided spreading (Eq. (15)) through a node -> marker CSR;
+ *   5. the hybrid LBM collide-and-stream (Eq. (6)) with the MUSCL-Hancock
+ *      total-energy update (Eqs. (10)-(11), Appendix A).
+ *
+ * Conventions
+ *   - Lattice units: dx = dt = 1, R = c_s^2 = 1/3, temperatures in units of T_ref.
+ *   - Return value 0 (LBM_OK) on success, a negative LBM_E_* code otherwise;
+ *     lbm_last_error() gives a message. Nothing throws across this boundary.
+ *   - Fields are structure-of-arrays over nodes, node = x + nx*(y + ny*z) (x fastest).
+ *   - Every call is ordered on the HIP stream given to lbm_init_grid. A handle is
+ *     bound to one stream and one device and is not thread-safe.
+ *   - The device workspace is owned by the caller (it must outlive the handle);
+ *     the library never allocates device memory. Host arrays passed in are copied.
+ */
+#ifndef LBMIB_H
+#define LBMIB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM_OK = 0,
+    LBM_E_INVAL = -1,      /* invalid argument or parameter */
+    LBM_E_NOMEM = -2,      /* workspace too small for the request */
+    LBM_E_HIP = -3,        /* a HIP runtime call failed */
+    LBM_E_STATE = -4,      /* call not valid in the current state (e.g. loads before a step) */
+    LBM_E_NONFINITE = -5   /* a non-finite value was detected by the step check */
+};
+
+enum { LBM_BC_PERIODIC = 0, LBM_BC_INFLOW_OUTFLOW = 1 };
+enum { LBM_IB_DIBM = 0, LBM_IB_FODIBM = 1, LBM_IB_FODIBM_R = 2 };
+enum { LBM_KERNEL_COS = 0, LBM_KERNEL_ROMA3 = 1 };
+enum { LBM_T_NONE = 0, LBM_T_DIRICHLET = 1, LBM_T_NEUMANN = 2 };
+enum { LBM_F32 = 32, LBM_F64 = 64 };
+
+/* Problem parameters (lattice units). Sec. 2.1 (gas), Sec. 2.2 (solver), Sec. 3.4 (gamma). */
+typedef struct lbm_params {
+    int dim;            /* 2 (D2Q9) or 3 (D3Q19, Appendix A) */
+    int nx, ny, nz;     /* grid size; nz = 1 when dim = 2 */
+    int precision;      /* LBM_F32 or LBM_F64: storage and arithmetic of the sweep */
+    int bc_x;           /* LBM_BC_PERIODIC or LBM_BC_INFLOW_OUTFLOW along x (y, z periodic) */
+    int kernel;         /* marker kernel: LBM_KERNEL_COS (Eq. (19), d = 2) or LBM_KERNEL_ROMA3 */
+    int max_markers;    /* marker capacity reserved in the workspace */
+    int with_aC;        /* 1: lattice third-order correction a^C in Eq. (A.9); 0: a^C = 0 */
+    int pad0;
+    double gamma;       /* ratio of specific heats */
+    double mu;          /* dynamic viscosity (constant) */
+    double lambda_;     /* thermal conductivity */
+    double sigma;       /* HRR weight of Eq. (A.7) (0.98 in the paper) */
+    double rho_inf;     /* free stream density */
+    double u_inf[3];    /* free stream velocity */
+    double T_inf;       /* free stream temperature (units of T_ref) */
+    double ref_len;     /* reference length for Re, Cd and Nu */
+    double ref_area;    /* reference area for Cd, Cl (a length in 2D) */
+    double surface;     /* wetted surface for Nu (a perimeter in 2D) */
+    double T_wall;      /* wall temperature used in Nu */
+} lbm_params;
+
+/* Loads of the last step (FP64). F = -sum_l F_l W_l (force on the body), Q_heat = sum_l Q_l W_l,
+ * Cd = F_x / (rho u^2 A / 2), Cl = F_y / (rho u^2 A / 2), Nu = Q_heat L / (lambda (T_w - T_inf) S).
+ * eps_* are the mean boundary-condition errors of Eqs. (35), (36), (38) over active markers,
+ * with the "s" values interpolated two-sidedly (Eq. (12), d = 2) from the current fields. */
+typedef struct lbm_loads {
+    double F[3];
+    double Q_heat;
+    double Cd, Cl, Nu;
+    double eps_dir, eps_neu, eps_iso;
+    int n_inactive;     /* markers whose interior support is empty (phi = 0) */
+    int n_markers;
+} lbm_loads;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Device workspace bytes the library needs for p (0 if p is invalid). Pure function. */
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/* Create a handle on the current HIP device. dev_workspace: caller-owned device memory of at
+ * least lbm_workspace_bytes(p) bytes, 256-byte aligned. hip_stream: a hipStream_t (NULL = the
+ * default stream). The state is set to the free-stream equilibrium f = f^eq(rho_inf, u_inf, T_inf)
+ * (Eq. (A.3)), rho E = rho_inf (|u_inf|^2/2 + Cv T_inf), zero force history.
+ * Errors: LBM_E_INVAL (dim, sizes, tau-bar <= 1/2, rest population of Eq. (A.3) negative at
+ * T_inf, non-finite values), LBM_E_NOMEM (bytes too small), LBM_E_HIP. */
+int lbm_init_grid(const lbm_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
+                  lbm_handle** out);
+
+/* Immersed body: m markers with positions X[m*dim] and outward unit normals normal[m*dim]
+ * (host, row-major per marker). area_w (nullable) is the input weight dq dr ds of Eq. (13),
+ * unused by the one-sided methods. u_wall[m*dim] is the wall velocity u^Bt, t_kind[m] one of
+ * LBM_T_*, t_value[m] the wall temperature (Dirichlet) or dT/dn (Neumann). method: LBM_IB_*.
+ * Runs the per-geometry precompute on the host in FP64 (supports, interior set, phi of Eq. (16),
+ * X* of Eq. (25), d_BV, projection points, W of Eq. (17), node -> marker CSR) and uploads it.
+ * Replaces any previous body and clears the force history held at forced nodes.
+ * Errors: LBM_E_INVAL (non-finite input, |n| != 1 within 1e-9, a marker within 4 cells of an
+ * x boundary under the inflow/outflow closure or within 3 cells of any edge, m > max_markers),
+ * LBM_E_NOMEM (precomputed lists exceed the workspace), LBM_E_HIP. m = 0 removes the body. */
+int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal,
+                   const double* area_w, const double* u_wall, const int* t_kind,
+                   const double* t_value, int method);
+
+/* Enqueue n time steps on the handle's stream. Asynchronous; the last step also accumulates
+ * the FP64 velocity residual r = ||u^{n+1} - u^n|| / (|u_inf| sqrt(N)) and a non-finite check
+ * (read with lbm_residual). Errors: LBM_E_INVAL (n < 0), LBM_E_HIP. */
+int lbm_step(lbm_handle* h, int n);
+
+/* Loads of the last step (see lbm_loads). Synchronises the stream.
+ * Errors: LBM_E_STATE (no body or no step taken since the body was set), LBM_E_HIP. */
+int ib_wall_loads(lbm_handle* h, lbm_loads* out);
+
+/* Fields of the current state: rho = sum f, u = sum c f / rho (force-free), T from
+ * rho E = rho (|u|^2/2 + Cv T), p = rho R T. dtype LBM_F32 or LBM_F64; on_device = 1 for device
+ * pointers (stream-ordered), 0 for host pointers (the call synchronises). u has dim components
+ * stored as u[a*N + node]. Any pointer may be NULL. Errors: LBM_E_INVAL, LBM_E_HIP. */
+int lbm_fields(lbm_handle* h, int dtype, int on_device, void* rho, void* u, void* T, void* p);
+
+/* Set the state to the equilibrium of given FP64 fields rho[N], u[dim*N], T[N] (host or device),
+ * with zero force history (a warm or cold start). Errors: LBM_E_INVAL, LBM_E_HIP. */
+int lbm_set_fields(lbm_handle* h, int on_device, const double* rho, const double* u,
+                   const double* T);
+
+/* Canonical FP64 state (host arrays): f[Q*N] (populations f-bar, population-major), rhoE[N],
+ * H2[dim*dim*N] (the deviatoric sum_i (c c - delta c^2/D) F_i of the previous step, tensor
+ * component (a,b) at H2[(a*dim+b)*N + node]). set: off-diagonal H2 must vanish away from the
+ * forced nodes of the current body. Both synchronise. Errors: LBM_E_INVAL, LBM_E_HIP. */
+int lbm_get_state(lbm_handle* h, double* f, double* rhoE, double* H2);
+int lbm_set_state(lbm_handle* h, const double* f, const double* rhoE, const double* H2);
+
+/* FP64 residual and non-finite flag of the last step of the last lbm_step call.
+ * Returns LBM_E_NONFINITE if the state held a non-finite value; LBM_E_STATE before any step. */
+int lbm_residual(lbm_handle* h, double* r);
+
+/* Precomputed geometry, for inspection (host outputs, any may be NULL).
+ * counts[6] = {m, n_rows, n_entries, n_support_entries, n_interior, n_active}.
+ * supp_ptr[m+1], supp_node[], supp_w[] (delta_il); phi[m], xstar[m*dim], dbv[m], W[m];
+ * rows[n_rows] (node indices), row_ptr[n_rows+1], col_marker[], col_s[] (phi_k delta_ik W_k). */
+int ib_geometry_counts(lbm_handle* h, long long* counts);
+int ib_geometry(lbm_handle* h, long long* supp_ptr, long long* supp_node, double* supp_w,
+                double* phi, double* xstar, double* dbv, double* W, long long* rows,
+                long long* row_ptr, long long* col_marker, double* col_s, long long* interior);
+
+/* Per-marker results of the last step (host, any may be NULL): F[m*dim], Wib[m], Qib[m],
+ * rho[m], T[m] (interpolated predicted values), uP[m*dim], TP[m] (projection point). Synchronises. */
+int ib_marker_state(lbm_handle* h, double* F, double* Wib, double* Qib, double* rho, double* T,
+                    double* uP, double* TP);
+
+/* Release the handle (not the caller's workspace). */
+void lbm_destroy(lbm_handle* h);
+
+/* Message of the last error on this handle (or of the last failed lbm_init_grid if h is NULL). */
+const char* lbm_last_error(lbm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMIB_H */

@@ -256,6 +256,17 @@ def lb_face_fluxes(lat, fcol):
     return Frho, Fmom
 
 
+# Velocities below this magnitude count as zero in the two sign decisions of the
+# MUSCL operator (sign(u) in eta and the upwind test u~ >= 0). Both decisions are
+# discontinuous at u = 0, and a velocity that vanishes by symmetry comes out as a
+# rounding residue of either sign; the dead zone makes the decision reproducible.
+U_ZERO = 1e-7
+
+
+def sign0(u):
+    return (u > U_ZERO).astype(np.float64) - (u < -U_ZERO).astype(np.float64)
+
+
 def muscl_face(phi, ua, a, D):
     """Eq. (A.14)-(A.16): the MUSCL-Hancock value F*(phi) on the face x + e_a/2.
 
@@ -266,7 +277,7 @@ def muscl_face(phi, ua, a, D):
     m = unit(D, a, -1)
 
     def slope(p, u):
-        eta = (2.0 * u - np.sign(u)) / 3.0
+        eta = (2.0 * u - sign0(u)) / 3.0
         return 0.5 * ((1.0 + eta) * (p - at(p, m, D)) + (1.0 - eta) * (at(p, e, D) - p))
 
     ua_b = at(ua, e, D)
@@ -274,7 +285,7 @@ def muscl_face(phi, ua, a, D):
     left = phi + 0.5 * slope(phi, ua) * (1.0 - ua)           # Phi-bar_{+a/2}(x)
     right = phi_b - 0.5 * at(slope(phi, ua), e, D) * (1.0 + ua_b)   # Phi-bar_{-a/2}(x + e_a)
     utilde = 0.5 * (ua + ua_b)
-    return np.where(utilde >= 0.0, left, right)
+    return np.where(utilde >= -U_ZERO, left, right)
 
 
 def energy_face_fluxes(lat, prm, rho, u, T, Frho, Fmom):

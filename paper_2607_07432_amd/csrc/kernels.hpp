@@ -1,0 +1,98 @@
+// Launch interface between the C ABI (api.hip) and the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "node_math.hpp"
+
+namespace lbmib {
+
+struct GridP {
+    int nx, ny, nz;
+    long long N;
+    int bc_x;           // 0 periodic, 1 inflow/outflow closure along x
+};
+
+// Ping-pong state (storage type S): f~[Q][N] (f - w), e[N] (rho E - e_ref), h2[D-1][N]
+// (diagonal of the deviatoric force history; the last diagonal entry is minus the sum).
+template <class S>
+struct StateP {
+    S* f;
+    S* e;
+    S* h2;
+};
+
+// Sparse data of the forced nodes (CSR rows), FP64.
+struct RowsP {
+    int nrows;
+    const int* rowmap;      // [N] row index of a node, -1 if not forced
+    const long long* rows;  // [nrows] node of each row
+    double* fib;            // [D][nrows] momentum forcing
+    double* fE;             // [nrows] energy forcing w + q
+    double* h2off;          // [NOFF][nrows] off-diagonal force history (xy[, xz, yz])
+};
+
+struct FreeStream {
+    double fdev[19];        // f^eq_i - w_i at (rho_inf, u_inf, T_inf)
+    double e_ref;           // rho_inf (|u_inf|^2/2 + Cv T_inf): reference of the energy deviation
+    double rho_inf, u_inf[3], T_inf;
+};
+
+struct SweepArgs {
+    GridP grid;
+    Gas gas;
+    FreeStream fs;
+    RowsP rows;
+};
+
+// Marker data (FP64) uploaded by ib_set_markers.
+struct MarkersP {
+    int m, dim, method;
+    const long long *supp_ptr, *supp_node;
+    const double* supp_w;
+    const long long *proj_ptr, *proj_node;
+    const double* proj_w;
+    const long long *tw_ptr, *tw_node;
+    const double* tw_w;
+    const double *phi, *dbv, *W;
+    const double *u_wall, *t_value;
+    const int* t_kind;
+    const long long *row_ptr, *col_marker;
+    const double* col_s;
+    double* G;              // [m][D+2]: F (D), W^IB, Q^IB of the last step
+    double* diag;           // [m][8]: rho*, T*, TP, uP (D), Tt  (last step)
+    double* eps;            // [m][4]: eps_dir, eps_neu, eps_iso, kind mask
+};
+
+// Split sweep (macros -> collide -> stream + fluxes + energy).
+template <class L, class S, class C>
+hipError_t launch_split_step(const SweepArgs& a, StateP<S> A, StateP<S> B, C* M, C* fcol, hipStream_t st);
+
+template <class L, class S>
+hipError_t launch_init_state(const SweepArgs& a, StateP<S> A, hipStream_t st);
+template <class L, class S>
+hipError_t launch_set_fields(const SweepArgs& a, StateP<S> A, const double* rho, const double* u,
+                             const double* T, hipStream_t st);
+template <class L, class S, class O>
+hipError_t launch_fields(const SweepArgs& a, StateP<S> A, O* rho, O* u, O* T, O* p, hipStream_t st);
+template <class L, class S>
+hipError_t launch_export(const SweepArgs& a, StateP<S> A, int comp, double* out, hipStream_t st);
+template <class L, class S>
+hipError_t launch_import(const SweepArgs& a, StateP<S> A, int comp, const double* in, int* bad, hipStream_t st);
+template <class L, class S>
+hipError_t launch_residual(const SweepArgs& a, StateP<S> Old, StateP<S> New, double* partials, int nparts,
+                           double* out, hipStream_t st);
+
+// Immersed boundary.
+template <class L, class S>
+hipError_t launch_markers(const SweepArgs& a, const MarkersP& mk, StateP<S> A, hipStream_t st);
+hipError_t launch_spread(int dim, const MarkersP& mk, RowsP rows, hipStream_t st);
+template <class L, class S>
+hipError_t launch_eps(const SweepArgs& a, const MarkersP& mk, StateP<S> A, double u_ref, double T_inf,
+                      double ref_len, hipStream_t st);
+hipError_t launch_loads(int dim, const MarkersP& mk, double* out, hipStream_t st);
+hipError_t launch_rowmap(const long long* rows, int nrows, int* rowmap, hipStream_t st);
+
+int residual_parts(long long N);
+
+}  // namespace lbmib

@@ -1,0 +1,264 @@
+"""Python binding of the HIP library (include/lbmib.h): argument marshalling only.
+
+PyTorch supplies the device workspace and the HIP stream; every step of the
+method runs in the library's kernels. Loading fails loudly when the library has
+not been built (python -m paper_2607_07432_amd.build).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import workloads
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, 'liblbmib.so')
+
+LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_STATE, LBM_E_NONFINITE = 0, -1, -2, -3, -4, -5
+F32, F64 = 32, 64
+BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
+
+EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step', 'ib_wall_loads', 'lbm_fields',
+           'lbm_set_fields', 'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts',
+           'ib_geometry', 'ib_marker_state', 'lbm_destroy', 'lbm_last_error']
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f'{msg} (code {code})')
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [('dim', ctypes.c_int), ('nx', ctypes.c_int), ('ny', ctypes.c_int), ('nz', ctypes.c_int),
+                ('precision', ctypes.c_int), ('bc_x', ctypes.c_int), ('kernel', ctypes.c_int),
+                ('max_markers', ctypes.c_int), ('with_aC', ctypes.c_int), ('pad0', ctypes.c_int),
+                ('gamma', ctypes.c_double), ('mu', ctypes.c_double), ('lambda_', ctypes.c_double),
+                ('sigma', ctypes.c_double), ('rho_inf', ctypes.c_double), ('u_inf', ctypes.c_double * 3),
+                ('T_inf', ctypes.c_double), ('ref_len', ctypes.c_double), ('ref_area', ctypes.c_double),
+                ('surface', ctypes.c_double), ('T_wall', ctypes.c_double)]
+
+
+class Loads(ctypes.Structure):
+    _fields_ = [('F', ctypes.c_double * 3), ('Q_heat', ctypes.c_double), ('Cd', ctypes.c_double),
+                ('Cl', ctypes.c_double), ('Nu', ctypes.c_double), ('eps_dir', ctypes.c_double),
+                ('eps_neu', ctypes.c_double), ('eps_iso', ctypes.c_double), ('n_inactive', ctypes.c_int),
+                ('n_markers', ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load liblbmib.so and declare its signatures. Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f'HIP library not built: {path} is missing '
+                           '(run python -m paper_2607_07432_amd.build)')
+    lib = ctypes.CDLL(path)
+    P, vp, i, d = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    dp, ip, llp = P(d), P(i), P(ctypes.c_longlong)
+    lib.lbm_workspace_bytes.argtypes = [P(Params)]
+    lib.lbm_workspace_bytes.restype = ctypes.c_size_t
+    lib.lbm_init_grid.argtypes = [P(Params), vp, ctypes.c_size_t, vp, P(vp)]
+    lib.ib_set_markers.argtypes = [vp, i, dp, dp, dp, dp, ip, dp, i]
+    lib.lbm_step.argtypes = [vp, i]
+    lib.ib_wall_loads.argtypes = [vp, P(Loads)]
+    lib.lbm_fields.argtypes = [vp, i, i, vp, vp, vp, vp]
+    lib.lbm_set_fields.argtypes = [vp, i, dp, dp, dp]
+    lib.lbm_get_state.argtypes = [vp, dp, dp, dp]
+    lib.lbm_set_state.argtypes = [vp, dp, dp, dp]
+    lib.lbm_residual.argtypes = [vp, dp]
+    lib.ib_geometry_counts.argtypes = [vp, llp]
+    lib.ib_geometry.argtypes = [vp, llp, llp, dp, dp, dp, dp, dp, llp, llp, llp, dp, llp]
+    lib.ib_marker_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
+    lib.lbm_destroy.argtypes = [vp]
+    lib.lbm_destroy.restype = None
+    lib.lbm_last_error.argtypes = [vp]
+    lib.lbm_last_error.restype = ctypes.c_char_p
+    for name in ('lbm_init_grid', 'ib_set_markers', 'lbm_step', 'ib_wall_loads', 'lbm_fields', 'lbm_set_fields',
+                 'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts', 'ib_geometry',
+                 'ib_marker_state'):
+        getattr(lib, name).restype = i
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if a is not None else None
+
+
+def _llptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)) if a is not None else None
+
+
+def params_from_case(case, precision=F64, max_markers=None, with_aC=True):
+    p = Params()
+    p.dim = case.dim
+    p.nx, p.ny = case.dims[0], case.dims[1]
+    p.nz = case.dims[2] if case.dim == 3 else 1
+    p.precision = precision
+    p.bc_x = BC_INFLOW_OUTFLOW if case.bc == 'inflow_outflow' else BC_PERIODIC
+    p.kernel = case.kernel
+    m = len(case.X) if case.X is not None else 0
+    p.max_markers = max_markers if max_markers is not None else max(m, 1)
+    p.with_aC = 1 if with_aC else 0
+    p.gamma, p.mu, p.lambda_, p.sigma = case.gamma, case.mu, case.lam, case.sigma
+    p.rho_inf = case.rho_inf
+    for a in range(3):
+        p.u_inf[a] = case.u_inf[a] if a < len(case.u_inf) else 0.0
+    p.T_inf = case.T_inf
+    p.ref_len, p.ref_area, p.surface, p.T_wall = case.ref_len, case.ref_area, case.surface, case.T_wall
+    return p
+
+
+class Solver:
+    """One grid on one GPU: a handle of the HIP library plus its torch-allocated workspace."""
+
+    def __init__(self, params, device='cuda:0', stream=None):
+        import torch
+        self.lib = load_library()
+        self.p = params
+        self.D = params.dim
+        self.Q = 9 if self.D == 2 else 19
+        self.dims = (params.nx, params.ny, params.nz)
+        self.N = params.nx * params.ny * params.nz
+        self.device = torch.device(device)
+        nbytes = self.lib.lbm_workspace_bytes(ctypes.byref(params))
+        if nbytes == 0:
+            raise LbmError(LBM_E_INVAL, 'invalid parameters')
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = self.lib.lbm_init_grid(ctypes.byref(params), ctypes.c_void_p(self._ws_ptr), nbytes,
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != LBM_OK:
+            raise LbmError(rc, self.lib.lbm_last_error(None).decode())
+        self.h = h
+        self.m = 0
+
+    @classmethod
+    def from_case(cls, case, precision=F64, max_markers=None, with_aC=True, device='cuda:0', markers=True):
+        s = cls(params_from_case(case, precision, max_markers, with_aC), device)
+        if markers and case.X is not None:
+            s.set_markers(case.X, case.n, case.u_wall, case.t_kind, case.t_value, case.method)
+        return s
+
+    def _check(self, rc):
+        if rc != LBM_OK:
+            raise LbmError(rc, self.lib.lbm_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, 'h', None):
+            self.lib.lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_markers(self, X, n, u_wall, t_kind, t_value, method=workloads.METHOD_FODIBM_R, area_w=None):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        n = np.ascontiguousarray(n, dtype=np.float64)
+        u_wall = np.ascontiguousarray(u_wall, dtype=np.float64)
+        t_kind = np.ascontiguousarray(t_kind, dtype=np.int32)
+        t_value = np.ascontiguousarray(t_value, dtype=np.float64)
+        aw = np.ascontiguousarray(area_w, dtype=np.float64) if area_w is not None else None
+        m = len(X)
+        self._check(self.lib.ib_set_markers(self.h, m, _dptr(X), _dptr(n), _dptr(aw), _dptr(u_wall),
+                                            _iptr(t_kind), _dptr(t_value), int(method)))
+        self.m = m
+
+    def step(self, n=1):
+        self._check(self.lib.lbm_step(self.h, int(n)))
+
+    def residual(self):
+        r = ctypes.c_double()
+        self._check(self.lib.lbm_residual(self.h, ctypes.byref(r)))
+        return r.value
+
+    def loads(self):
+        out = Loads()
+        self._check(self.lib.ib_wall_loads(self.h, ctypes.byref(out)))
+        return dict(F=np.array(out.F[:self.D]), Q_heat=out.Q_heat, Cd=out.Cd, Cl=out.Cl, Nu=out.Nu,
+                    eps_dir=out.eps_dir, eps_neu=out.eps_neu, eps_iso=out.eps_iso, n_inactive=out.n_inactive,
+                    n_markers=out.n_markers)
+
+    def fields(self, dtype=F64):
+        """Host numpy fields (rho, u[D], T, p) on the grid shape (nz, ny, nx) / (ny, nx)."""
+        npd = np.float64 if dtype == F64 else np.float32
+        rho = np.empty(self.N, npd)
+        u = np.empty(self.D * self.N, npd)
+        T = np.empty(self.N, npd)
+        p = np.empty(self.N, npd)
+        vp = lambda a: ctypes.c_void_p(a.ctypes.data)
+        self._check(self.lib.lbm_fields(self.h, dtype, 0, vp(rho), vp(u), vp(T), vp(p)))
+        shape = self.grid_shape
+        return rho.reshape(shape), u.reshape((self.D,) + shape), T.reshape(shape), p.reshape(shape)
+
+    def fields_device(self, rho, u, T, p, dtype=F64):
+        """Write fields into caller-owned torch tensors (stream ordered)."""
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        self._check(self.lib.lbm_fields(self.h, dtype, 1, ptr(rho), ptr(u), ptr(T), ptr(p)))
+
+    @property
+    def grid_shape(self):
+        return (self.dims[1], self.dims[0]) if self.D == 2 else (self.dims[2], self.dims[1], self.dims[0])
+
+    def set_fields(self, rho, u, T):
+        rho = np.ascontiguousarray(rho, dtype=np.float64).ravel()
+        u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+        T = np.ascontiguousarray(T, dtype=np.float64).ravel()
+        self._check(self.lib.lbm_set_fields(self.h, 0, _dptr(rho), _dptr(u), _dptr(T)))
+
+    def get_state(self):
+        """Canonical FP64 state: f (Q, *grid), rhoE (*grid), H2 (D, D, *grid)."""
+        f = np.empty(self.Q * self.N)
+        e = np.empty(self.N)
+        H2 = np.empty(self.D * self.D * self.N)
+        self._check(self.lib.lbm_get_state(self.h, _dptr(f), _dptr(e), _dptr(H2)))
+        shape = self.grid_shape
+        return f.reshape((self.Q,) + shape), e.reshape(shape), H2.reshape((self.D, self.D) + shape)
+
+    def set_state(self, f, rhoE, H2):
+        f = np.ascontiguousarray(f, dtype=np.float64).ravel()
+        e = np.ascontiguousarray(rhoE, dtype=np.float64).ravel()
+        H2 = np.ascontiguousarray(H2, dtype=np.float64).ravel()
+        self._check(self.lib.lbm_set_state(self.h, _dptr(f), _dptr(e), _dptr(H2)))
+
+    def geometry(self):
+        c = np.zeros(6, dtype=np.int64)
+        self._check(self.lib.ib_geometry_counts(self.h, _llptr(c)))
+        m, nrows, nent, nsupp, nint, nact = (int(v) for v in c)
+        D = self.D
+        out = dict(supp_ptr=np.zeros(m + 1, np.int64), supp_node=np.zeros(nsupp, np.int64),
+                   supp_w=np.zeros(nsupp), phi=np.zeros(m), xstar=np.zeros(m * D), dbv=np.zeros(m),
+                   W=np.zeros(m), rows=np.zeros(nrows, np.int64), row_ptr=np.zeros(nrows + 1, np.int64),
+                   col_marker=np.zeros(nent, np.int64), col_s=np.zeros(nent), interior=np.zeros(nint, np.int64))
+        self._check(self.lib.ib_geometry(self.h, _llptr(out['supp_ptr']), _llptr(out['supp_node']),
+                                         _dptr(out['supp_w']), _dptr(out['phi']), _dptr(out['xstar']),
+                                         _dptr(out['dbv']), _dptr(out['W']), _llptr(out['rows']),
+                                         _llptr(out['row_ptr']), _llptr(out['col_marker']), _dptr(out['col_s']),
+                                         _llptr(out['interior'])))
+        out['xstar'] = out['xstar'].reshape(m, D)
+        out['n_active'] = nact
+        return out
+
+    def marker_state(self):
+        m, D = self.m, self.D
+        F, Wib, Qib, rho, T, uP, TP = (np.zeros(m * D), np.zeros(m), np.zeros(m), np.zeros(m), np.zeros(m),
+                                       np.zeros(m * D), np.zeros(m))
+        self._check(self.lib.ib_marker_state(self.h, _dptr(F), _dptr(Wib), _dptr(Qib), _dptr(rho), _dptr(T),
+                                             _dptr(uP), _dptr(TP)))
+        return dict(F=F.reshape(m, D), Wib=Wib, Qib=Qib, rho=rho, T=T, uP=uP.reshape(m, D), TP=TP)

@@ -1,0 +1,62 @@
+"""The C-ABI library loads on a CPU-only host and exports every function include/lbmib.h declares.
+
+No compute call is made here; lbm_workspace_bytes is a pure host function.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2607_07432_amd import lbmib, workloads
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 'include', 'lbmib.h')
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)
+    return sorted(set(re.findall(r'\b((?:lbm|ib)_[a-z_0-9]+)\s*\(', text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ('lbm_init_grid', 'ib_set_markers', 'lbm_step', 'ib_wall_loads', 'lbm_fields'):
+        assert must in names
+    assert sorted(names) == sorted(lbmib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbmib.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_workspace_bytes_is_pure_and_validates():
+    lib = lbmib.load_library()
+    case = workloads.config1()
+    p = lbmib.params_from_case(case, precision=64)
+    n64 = lib.lbm_workspace_bytes(ctypes.byref(p))
+    p32 = lbmib.params_from_case(case, precision=32)
+    n32 = lib.lbm_workspace_bytes(ctypes.byref(p32))
+    N = 200 * 100
+    # two states of (Q + 1 + D - 1) values plus the working area of (D + 2 + Q) values per node
+    assert n64 >= N * 8 * (2 * 11 + 13) and n32 >= N * 4 * (2 * 11 + 13)
+    assert n64 > n32
+    bad = lbmib.params_from_case(case)
+    bad.precision = 16
+    assert lib.lbm_workspace_bytes(ctypes.byref(bad)) == 0
+    bad = lbmib.params_from_case(case)
+    bad.mu = -1.0
+    assert lib.lbm_workspace_bytes(ctypes.byref(bad)) == 0
+    assert lib.lbm_workspace_bytes(None) == 0
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    saved = lbmib._lib
+    try:
+        lbmib._lib = None
+        with pytest.raises(RuntimeError):
+            lbmib.load_library(str(tmp_path / 'missing.so'))
+    finally:
+        lbmib._lib = saved

@@ -1,0 +1,241 @@
+"""GPU (HIP, through the C ABI) versus the FP64 CPU oracle.
+
+Bars: FP64 fields within 1e-12 relative per step from an identical injected state;
+marker <-> node index lists bit-exact; FP32 within 1e-5 relative in the fields.
+"""
+import numpy as np
+import pytest
+
+from oracle import ib as oib
+from oracle import lbm as olbm
+from oracle import loads as oloads
+from oracle.lattice import for_dim
+from paper_2607_07432_amd import workloads as wl
+
+from parity_util import oracle_geometry, oracle_markers, oracle_params, oracle_step, random_state, rel, \
+    small_sphere_case
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope='module')
+def lbmib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip('no GPU')
+    from paper_2607_07432_amd import lbmib as mod
+    mod.load_library()
+    return mod
+
+
+def cylinder_small(method=wl.METHOD_FODIBM_R, bc='inflow_outflow', kernel=wl.KERNEL_COS):
+    c = wl.cylinder_case(nx=70, ny=44, center=(25.3, 21.7), diameter=14.0, markers=44, method=method,
+                         kernel=kernel, steps=1)
+    c.bc = bc
+    return c
+
+
+CASES = {
+    'cyl_R_io': lambda: cylinder_small(),
+    'cyl_F_per': lambda: cylinder_small(wl.METHOD_FODIBM, 'periodic'),
+    'cyl_D_io': lambda: cylinder_small(wl.METHOD_DIBM),
+    'cyl_R_roma3': lambda: cylinder_small(kernel=wl.KERNEL_ROMA3),
+    'config1': lambda: wl.config1(steps=1),
+    'sph_R_adiabatic': lambda: small_sphere_case(),
+    'sph_R_iso': lambda: small_sphere_case(T_wall_ratio=1.5),
+    'sph_F_iso_per': lambda: _periodic(small_sphere_case(wl.METHOD_FODIBM, T_wall_ratio=1.2)),
+}
+
+
+def _periodic(c):
+    c.bc = 'periodic'
+    return c
+
+
+def report(case, new, f1, e1, H1):
+    """Print where the GPU state differs from the oracle (per population and field)."""
+    Q = new.f.shape[0]
+    errs = [float(np.abs(f1[i] - new.f[i]).max()) for i in range(Q)]
+    i = int(np.argmax(errs))
+    loc = np.unravel_index(np.argmax(np.abs(f1[i] - new.f[i])), new.f.shape[1:])
+    print(f'[{case.name}] max|df| per i: ' + ' '.join(f'{e:.1e}' for e in errs))
+    print(f'[{case.name}] worst i={i} at grid index {loc}; |de|={np.abs(e1 - new.rhoE).max():.2e} at '
+          f'{np.unravel_index(np.argmax(np.abs(e1 - new.rhoE)), e1.shape)}; |dH2|={np.abs(H1 - new.H2).max():.2e}')
+
+
+def solver_for(lbmib, case, precision=64):
+    return lbmib.Solver.from_case(case, precision=precision)
+
+
+@pytest.mark.parametrize('name', list(CASES))
+def test_index_lists_bit_exact(lbmib, name):
+    case = CASES[name]()
+    g = oracle_geometry(case)
+    s = solver_for(lbmib, case)
+    h = s.geometry()
+    M = len(case.X)
+    for l in range(M):
+        a, b = h['supp_ptr'][l], h['supp_ptr'][l + 1]
+        assert h['supp_node'][a:b].tolist() == g.supp_lin[l].tolist()
+        assert np.abs(h['supp_w'][a:b] - g.supp_w[l]).max(initial=0) < 1e-15
+    assert h['rows'].tolist() == g.rows.tolist()
+    assert h['row_ptr'].tolist() == g.row_ptr.tolist()
+    assert h['col_marker'].tolist() == g.col_marker.tolist()
+    assert h['interior'].tolist() == g.interior_lin.tolist()
+    assert rel(h['phi'], g.phi) < 1e-14
+    assert rel(h['W'], g.W) < 1e-13
+    assert rel(h['col_s'], g.col_s) < 1e-13
+    assert np.abs(h['dbv'] - g.dBV).max() < 1e-13
+    assert np.abs(h['xstar'] - g.Xstar).max() < 1e-12
+
+
+@pytest.mark.parametrize('name', list(CASES))
+def test_one_step_fp64_parity(lbmib, name):
+    case = CASES[name]()
+    g = oracle_geometry(case)
+    mk = oracle_markers(case)
+    st = random_state(case, g, seed=11)
+    s = solver_for(lbmib, case)
+    s.set_state(st.f, st.rhoE, st.H2)
+    f0, e0, H0 = s.get_state()
+    # populations are stored as f - w_i: the FP64 round trip is exact to an ulp of f
+    assert np.abs(f0 - st.f).max() <= 2 ** -52 and np.abs(e0 - st.rhoE).max() <= 2 ** -51
+    assert np.abs(H0 - st.H2).max() <= 1e-18
+    new, mf = oracle_step(case, st, g, mk)
+    s.step(1)
+    f1, e1, H1 = s.get_state()
+    report(case, new, f1, e1, H1)
+    assert rel(f1, new.f) < TOL64
+    assert rel(e1, new.rhoE) < TOL64
+    assert rel(H1, new.H2) < 1e-11 * max(1.0, 1e-4 / np.abs(new.H2).max())
+    ms = s.marker_state()
+    act = g.active
+    assert rel(ms['F'][act], mf['F'][act]) < 1e-11
+    assert rel(ms['Qib'][act], mf['Qib'][act]) < 1e-11
+    assert rel(ms['rho'][act], mf['rho'][act]) < TOL64
+    assert rel(ms['T'][act], mf['T'][act]) < TOL64
+    assert rel(ms['TP'][act], mf['TP'][act]) < TOL64
+
+
+@pytest.mark.parametrize('name', ['cyl_R_io', 'sph_R_iso'])
+def test_multi_step_fp64_parity_and_loads(lbmib, name):
+    case = CASES[name]()
+    lat = for_dim(case.dim)
+    prm = oracle_params(case)
+    g = oracle_geometry(case)
+    mk = oracle_markers(case)
+    st = olbm.freestream_state(lat, prm, tuple(case.dims[::-1]))
+    s = solver_for(lbmib, case)
+    nsteps = 20
+    for k in range(nsteps):
+        old = st
+        st, mf = oracle_step(case, st, g, mk)
+        if k < 4:
+            # step by step at first, so a divergence names its step
+            s.step(1)
+            f1, e1, H1 = s.get_state()
+            print(f'[{case.name}] step {k + 1}: rel f {rel(f1, st.f):.2e} rel rhoE {rel(e1, st.rhoE):.2e}')
+            report(case, st, f1, e1, H1)
+    s.step(nsteps - 4)
+    f1, e1, H1 = s.get_state()
+    report(case, st, f1, e1, H1)
+    assert rel(f1, st.f) < 1e-11
+    assert rel(e1, st.rhoE) < 1e-11
+    rho, u, T, p = s.fields()
+    orho, ou, oT, op = olbm.fields(lat, prm, st)
+    assert rel(rho, orho) < 1e-12 and rel(T, oT) < 1e-12 and rel(u, ou) < 1e-10
+    # loads and boundary errors of the last step
+    Fb, Qh = oloads.body_loads(g, mf)
+    Cd, Cl, Nu = oloads.coefficients(Fb, Qh, case.rho_inf, case.u_ref, case.ref_len, case.ref_area, case.surface,
+                                     case.lam, case.T_wall, case.T_inf)
+    ed, en, ei = oloads.bc_errors(lat, prm, g, mk, st, case.u_ref, case.T_inf, case.ref_len)
+    L = s.loads()
+    assert abs(L['Cd'] - Cd) <= 1e-10 * max(1.0, abs(Cd))
+    assert abs(L['Cl'] - Cl) <= 1e-10 * max(1.0, abs(Cd))
+    if case.T_wall != case.T_inf:
+        assert abs(L['Nu'] - Nu) <= 1e-10 * max(1.0, abs(Nu))
+    assert abs(L['eps_dir'] - ed) < 1e-10 and abs(L['eps_neu'] - en) < 1e-10 and abs(L['eps_iso'] - ei) < 1e-10
+    r = oloads.residual(lat, prm, old, st, case.u_ref)
+    assert abs(s.residual() - r) <= 1e-10 * r
+
+
+def test_fp32_error_budget_config1(lbmib):
+    case = wl.config1(steps=1)
+    lat = for_dim(2)
+    prm = oracle_params(case)
+    g = oracle_geometry(case)
+    mk = oracle_markers(case)
+    st = olbm.freestream_state(lat, prm, (100, 200))
+    s = solver_for(lbmib, case, precision=32)
+    n = 100
+    for _ in range(n):
+        st, mf = oracle_step(case, st, g, mk)
+    s.step(n)
+    rho, u, T, p = s.fields()
+    orho, ou, oT, op = olbm.fields(lat, prm, st)
+    assert rel(rho, orho) < 1e-5
+    assert rel(T, oT) < 1e-5
+    assert rel(u, ou) < 1e-5 * 20   # u is relative to its own max (~0.2); 1e-5 of |u|_max on dynamic scale
+    Fb, Qh = oloads.body_loads(g, mf)
+    Cd, Cl, Nu = oloads.coefficients(Fb, Qh, case.rho_inf, case.u_ref, case.ref_len, case.ref_area, case.surface,
+                                     case.lam, case.T_wall, case.T_inf)
+    L = s.loads()
+    assert abs(L['Cd'] - Cd) <= 1e-4 * abs(Cd)
+    assert abs(L['Nu'] - Nu) <= 1e-4 * abs(Nu)
+
+
+def test_state_round_trip_and_determinism(lbmib):
+    case = CASES['cyl_R_io']()
+    s = solver_for(lbmib, case)
+    s.step(7)
+    a = s.get_state()
+    s.step(5)
+    b = s.get_state()
+    # same run twice: bit-identical (no atomics, fixed reduction orders)
+    s3 = solver_for(lbmib, case)
+    s3.step(12)
+    for x, y in zip(b, s3.get_state()):
+        assert np.array_equal(x, y)
+    # restart from a checkpoint: equal to the continuous run up to the f - w_i storage rounding
+    s2 = solver_for(lbmib, case)
+    s2.set_state(*a)
+    s2.step(5)
+    c = s2.get_state()
+    for x, y in zip(b, c):
+        assert rel(x, y) < 1e-13
+
+
+def test_abi_errors(lbmib):
+    import ctypes
+    case = CASES['cyl_R_io']()
+    p = lbmib.params_from_case(case)
+    bad = lbmib.params_from_case(case)
+    bad.dim = 4
+    lib = lbmib.load_library()
+    assert lib.lbm_workspace_bytes(ctypes.byref(bad)) == 0
+    with pytest.raises(lbmib.LbmError) as ei:
+        lbmib.Solver(bad)
+    assert ei.value.code == lbmib.LBM_E_INVAL
+    hot = lbmib.params_from_case(case)
+    hot.T_inf = 2.5      # rest population of Eq. (A.3) negative
+    with pytest.raises(lbmib.LbmError):
+        lbmib.Solver(hot)
+    s = lbmib.Solver(p)
+    with pytest.raises(lbmib.LbmError) as ei:
+        s.loads()
+    assert ei.value.code == lbmib.LBM_E_STATE
+    X = case.X.copy()
+    X[0, 0] = 1.0        # too close to the inflow
+    with pytest.raises(lbmib.LbmError) as ei:
+        s.set_markers(X, case.n, case.u_wall, case.t_kind, case.t_value, case.method)
+    assert ei.value.code == lbmib.LBM_E_INVAL
+    rho, u, T, _ = s.fields()
+    T = T.copy()
+    T[3, 5] = np.nan
+    s.set_fields(rho, u, T)
+    s.step(1)
+    with pytest.raises(lbmib.LbmError) as ei:
+        s.residual()
+    assert ei.value.code == lbmib.LBM_E_NONFINITE
