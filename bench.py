@@ -1,0 +1,182 @@
+"""Throughput of the fused LBM + FODIBM-R time step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--precision 32|64] [--gpus 1]
+
+Workload: the 384 x 192 x 192 D3Q19 box with a D = 32 sphere (3217 Fibonacci markers,
+no-slip adiabatic wall, Ma 0.3, Re 300, FODIBM-R), inputs resident in HBM before the timed
+region. One step = marker interpolation + reconstruction + forces, spreading, and the grid
+sweep (collision, streaming, LB fluxes, MUSCL energy update), i.e. every row of the hot path.
+Prints one JSON line. The FP64 CPU oracle is timed beside it on a bounded crop of the same
+problem (the sphere in a 96 x 48 x 48 box).
+
+    python bench.py --copy-kernel BYTES
+
+runs only a plain device-to-device copy of BYTES bytes (the reference kernel that the
+rocprofv3 FETCH_SIZE / WRITE_SIZE counters are calibrated against).
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+
+
+def state_values_per_node(dim, q):
+    """Values of the minimal state one node update must read and write: populations,
+    rho E and the dense (diagonal, traceless) force history."""
+    return q + 1 + (dim - 1)
+
+
+def sweep_sources_hash():
+    h = hashlib.sha1()
+    for f in ('node_math.hpp', 'lattice.hpp', 'sweep_split.hip', 'sweep_fused.hip'):
+        p = os.path.join(ROOT, 'paper_2607_07432_amd', 'csrc', f)
+        if os.path.exists(p):
+            h.update(open(p, 'rb').read())
+    return h.hexdigest()[:12]
+
+
+def read_traffic(kernel_tag, hash_now):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel sources; None otherwise."""
+    path = os.path.join(ROOT, 'profiles', f'{kernel_tag}_traffic.md')
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith('|') and ':' not in line.split('|')[1]:
+            parts = [p.strip() for p in line.strip().strip('|').split('|')]
+            if len(parts) >= 2:
+                fields[parts[0]] = parts[1]
+    if fields.get('sources_hash') != hash_now:
+        return None
+    try:
+        return float(fields['hbm_bytes_per_launch'])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_kernel(nbytes):
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device='cuda:0')
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({'copy_bytes': n * 4, 'launches': 3}))
+
+
+def cpu_baseline(seconds_hint=20.0):
+    """FP64 oracle on a bounded crop: the same sphere (D = 32, 3217 markers) in 96 x 48 x 48."""
+    import numpy as np  # noqa: F401
+    from oracle import ib as oib
+    from oracle import lbm as olbm
+    from oracle.lattice import for_dim
+    from paper_2607_07432_amd import workloads as wl
+    case = wl.config2(nx=96, ny=48, nz=48, reynolds=300.0)
+    lat = for_dim(3)
+    prm = olbm.Params(mu=case.mu, lam=case.lam, gamma=case.gamma, sigma=case.sigma, rho_inf=case.rho_inf,
+                      u_inf=tuple(case.u_inf), T_inf=case.T_inf, bc=case.bc)
+    geom = oib.build_geometry(case.dims, case.X, case.n, case.method, case.kernel)
+    mk = oib.Markers(case.u_wall, case.t_kind, case.t_value)
+    st = olbm.freestream_state(lat, prm, tuple(case.dims[::-1]))
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        fib, fE, _ = oib.ib_step_forcing(lat, prm, geom, mk, st)
+        st = olbm.lbm_step(lat, prm, st, fib, fE)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > seconds_hint or steps >= 40:
+            break
+    glups = case.n_nodes * steps / el / 1e9
+    return {'value': glups, 'unit': 'GLUPS', 'cores': 1, 'kind': 'oracle',
+            'sample': f'FP64 NumPy oracle, sphere D=32 with 3217 markers in a 96x48x48 crop '
+                      f'({case.n_nodes} nodes), {steps} FODIBM-R steps in {el:.1f} s, single thread '
+                      f'({platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()})'}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=100)
+    ap.add_argument('--warmup', type=int, default=10)
+    ap.add_argument('--precision', type=int, default=32, choices=(32, 64))
+    ap.add_argument('--reynolds', type=float, default=300.0)
+    ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--copy-kernel', type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f'bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab '
+              'decomposition is a design, not part of this build.', file=sys.stderr)
+        sys.exit(2)
+    if args.copy_kernel:
+        copy_kernel(args.copy_kernel)
+        return
+
+    import torch
+    from paper_2607_07432_amd import lbmib
+    from paper_2607_07432_amd import workloads as wl
+
+    case = wl.config2(reynolds=args.reynolds)
+    solver = lbmib.Solver.from_case(case, precision=args.precision)
+    N = case.n_nodes
+    print(f'[bench] {case.name} {case.dims} N={N} markers={len(case.X)} precision=f{args.precision}',
+          file=sys.stderr, flush=True)
+
+    solver.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kernel_ms = solver.step_timed(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    glups = N * args.steps / (t1 - t0) / 1e9
+    resid = solver.residual()
+    loads = solver.loads()
+    print(f'[bench] {ms_per_step:.3f} ms/step, {glups:.2f} GLUPS, kernels (markers, spread, sweep) ms '
+          f'{kernel_ms.round(4).tolist()}, Cd {loads["Cd"]:.4f}, residual {resid:.3e}', file=sys.stderr, flush=True)
+
+    vals = state_values_per_node(3, 19)
+    bytes_per_node = 2 * vals * (args.precision // 8)
+    sweep_ms = float(kernel_ms[2])
+    achieved = bytes_per_node * N / (sweep_ms * 1e-3) / 1e9
+    tag = f'sweep_d3q19_f{args.precision}_384x192x192'
+    traffic = read_traffic(tag, sweep_sources_hash())
+    out = {
+        'metric': 'GLUPS of fused LBM+FODIBM step; time-to-steady warm vs cold at L2 tol',
+        'value': round(glups, 4), 'unit': 'GLUPS', 'n_gpus': 1, 'steps': args.steps, 'warmup': args.warmup,
+        'ms_per_step': round(ms_per_step, 5), 'higher_is_better': True, 'scaling': 'weak', 'vs_baseline': None,
+        'dtype': f'f{args.precision}', 'data': 'synthetic',
+        'config': {'workload': 'sphere3d: D3Q19 384x192x192, sphere D=32, 3217 markers, FODIBM-R, '
+                               f'adiabatic no-slip, Ma 0.3, Re {args.reynolds:g}, inflow/outflow in x',
+                   'nodes': N, 'markers': len(case.X), 'method': 'FODIBM-R', 'parallelism': 'single GPU'},
+        'roofline': {'bound': 'hbm', 'kernel': 'grid sweep (collision + streaming + fluxes + energy)',
+                     'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
+                     'frac': round(achieved / HBM_PEAK_GBS, 4),
+                     'bytes_per_node': bytes_per_node, 'sweep_ms': round(sweep_ms, 5),
+                     'traffic': traffic},
+        'kernel_ms': {'markers': round(float(kernel_ms[0]), 5), 'spread': round(float(kernel_ms[1]), 5),
+                      'sweep': round(sweep_ms, 5)},
+        'Cd': loads['Cd'], 'residual': resid,
+    }
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out['cpu_baseline'] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == '__main__':
+    main()

@@ -115,6 +115,12 @@ int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal,
  * (read with lbm_residual). Errors: LBM_E_INVAL (n < 0), LBM_E_HIP. */
 int lbm_step(lbm_handle* h, int n);
 
+/* As lbm_step, and also times the launches of every step with HIP events recorded on the
+ * handle's stream: kernel_ms[0] = marker interpolation + forces, kernel_ms[1] = spreading,
+ * kernel_ms[2] = the grid sweep (collision, streaming, fluxes, energy update), each the
+ * average per step in milliseconds. Synchronises. Errors: LBM_E_INVAL (n <= 0), LBM_E_HIP. */
+int lbm_step_timed(lbm_handle* h, int n, double* kernel_ms);
+
 /* Loads of the last step (see lbm_loads). Synchronises the stream.
  * Errors: LBM_E_STATE (no body or no step taken since the body was set), LBM_E_HIP. */
 int ib_wall_loads(lbm_handle* h, lbm_loads* out);

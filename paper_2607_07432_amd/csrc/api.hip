@@ -386,23 +386,31 @@ int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal, 
     return LBM_OK;
 }
 
-int lbm_step(lbm_handle* h, int n) {
-    if (!h) return LBM_E_INVAL;
-    if (n < 0) return fail(h, LBM_E_INVAL, "n < 0");
+namespace {
+
+// n steps; with ev (4 events per step) the marker, spread and sweep launches are bracketed.
+int run_steps(lbm_handle* h, int n, hipEvent_t* ev) {
     for (int s = 0; s < n; ++s) {
         const bool last = s == n - 1;
+        hipEvent_t* e4 = ev ? ev + 4 * s : nullptr;
         hipError_t e = dispatch(h, [&](auto L, auto S) {
             using LT = decltype(L);
             using ST = decltype(S);
             StateP<ST> A = current<ST>(h), B = other<ST>(h);
             hipError_t r = hipSuccess;
-            if (h->markers_set) {
+            if (e4) r = hipEventRecord(e4[0], h->stream);
+            if (h->markers_set && r == hipSuccess) {
                 r = launch_markers<LT, ST>(h->args, h->mk, A, h->stream);
+                if (r == hipSuccess && e4) r = hipEventRecord(e4[1], h->stream);
                 if (r == hipSuccess) r = launch_spread(h->D, h->mk, h->args.rows, h->stream);
+            } else if (e4 && r == hipSuccess) {
+                r = hipEventRecord(e4[1], h->stream);
             }
+            if (r == hipSuccess && e4) r = hipEventRecord(e4[2], h->stream);
             ST* M = (ST*)h->d.work;
             ST* fcol = M + (size_t)(h->D + 2) * h->N;
             if (r == hipSuccess) r = launch_split_step<LT, ST, ST>(h->args, A, B, M, fcol, h->stream);
+            if (r == hipSuccess && e4) r = hipEventRecord(e4[3], h->stream);
             if (r == hipSuccess && last)
                 r = launch_residual<LT, ST>(h->args, A, B, h->d.partials, residual_parts(h->N), h->d.resid,
                                             h->stream);
@@ -416,6 +424,36 @@ int lbm_step(lbm_handle* h, int n) {
         h->any_step = 1;
     }
     return LBM_OK;
+}
+
+}  // namespace
+
+int lbm_step(lbm_handle* h, int n) {
+    if (!h) return LBM_E_INVAL;
+    if (n < 0) return fail(h, LBM_E_INVAL, "n < 0");
+    return run_steps(h, n, nullptr);
+}
+
+int lbm_step_timed(lbm_handle* h, int n, double* kernel_ms) {
+    if (!h || !kernel_ms) return LBM_E_INVAL;
+    if (n <= 0) return fail(h, LBM_E_INVAL, "n must be positive");
+    std::vector<hipEvent_t> ev((size_t)4 * n);
+    for (auto& e : ev) HIPCHK(h, hipEventCreate(&e));
+    int rc = run_steps(h, n, ev.data());
+    if (rc == LBM_OK) {
+        hipError_t e = hipEventSynchronize(ev.back());
+        double acc[3] = {0, 0, 0};
+        for (int s = 0; s < n && e == hipSuccess; ++s)
+            for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+                float ms = 0;
+                e = hipEventElapsedTime(&ms, ev[4 * s + k], ev[4 * s + k + 1]);
+                acc[k] += ms;
+            }
+        if (e != hipSuccess) rc = fail(h, LBM_E_HIP, std::string("event timing: ") + hipGetErrorString(e));
+        for (int k = 0; k < 3; ++k) kernel_ms[k] = acc[k] / n;
+    }
+    for (auto& e : ev) hipEventDestroy(e);
+    return rc;
 }
 
 int lbm_residual(lbm_handle* h, double* r) {

@@ -18,7 +18,8 @@ LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_STATE, LBM_E_NONFINITE = 0, -
 F32, F64 = 32, 64
 BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
 
-EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step', 'ib_wall_loads', 'lbm_fields',
+EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step', 'lbm_step_timed',
+           'ib_wall_loads', 'lbm_fields',
            'lbm_set_fields', 'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts',
            'ib_geometry', 'ib_marker_state', 'lbm_destroy', 'lbm_last_error']
 
@@ -65,6 +66,7 @@ def load_library(path=LIB_PATH):
     lib.lbm_init_grid.argtypes = [P(Params), vp, ctypes.c_size_t, vp, P(vp)]
     lib.ib_set_markers.argtypes = [vp, i, dp, dp, dp, dp, ip, dp, i]
     lib.lbm_step.argtypes = [vp, i]
+    lib.lbm_step_timed.argtypes = [vp, i, dp]
     lib.ib_wall_loads.argtypes = [vp, P(Loads)]
     lib.lbm_fields.argtypes = [vp, i, i, vp, vp, vp, vp]
     lib.lbm_set_fields.argtypes = [vp, i, dp, dp, dp]
@@ -78,7 +80,7 @@ def load_library(path=LIB_PATH):
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.argtypes = [vp]
     lib.lbm_last_error.restype = ctypes.c_char_p
-    for name in ('lbm_init_grid', 'ib_set_markers', 'lbm_step', 'ib_wall_loads', 'lbm_fields', 'lbm_set_fields',
+    for name in ('lbm_init_grid', 'ib_set_markers', 'lbm_step', 'lbm_step_timed', 'ib_wall_loads', 'lbm_fields', 'lbm_set_fields',
                  'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts', 'ib_geometry',
                  'ib_marker_state'):
         getattr(lib, name).restype = i
@@ -182,6 +184,12 @@ class Solver:
 
     def step(self, n=1):
         self._check(self.lib.lbm_step(self.h, int(n)))
+
+    def step_timed(self, n):
+        """n steps; returns the average per-step ms of (markers, spread, sweep) from HIP events."""
+        ms = np.zeros(3)
+        self._check(self.lib.lbm_step_timed(self.h, int(n), _dptr(ms)))
+        return ms
 
     def residual(self):
         r = ctypes.c_double()
