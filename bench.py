@@ -114,6 +114,7 @@ def main():
     ap.add_argument('--reynolds', type=float, default=300.0)
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--copy-kernel', type=int, default=0)
+    ap.add_argument('--sweep', choices=('fused', 'threepass'), default='fused')
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -129,7 +130,8 @@ def main():
     from paper_2607_07432_amd import workloads as wl
 
     case = wl.config2(reynolds=args.reynolds)
-    solver = lbmib.Solver.from_case(case, precision=args.precision)
+    solver = lbmib.Solver.from_case(case, precision=args.precision,
+                                    sweep=lbmib.SWEEP_FUSED if args.sweep == 'fused' else lbmib.SWEEP_THREE_PASS)
     N = case.n_nodes
     print(f'[bench] {case.name} {case.dims} N={N} markers={len(case.X)} precision=f{args.precision}',
           file=sys.stderr, flush=True)
@@ -161,7 +163,7 @@ def main():
         'config': {'workload': 'sphere3d: D3Q19 384x192x192, sphere D=32, 3217 markers, FODIBM-R, '
                                f'adiabatic no-slip, Ma 0.3, Re {args.reynolds:g}, inflow/outflow in x',
                    'nodes': N, 'markers': len(case.X), 'method': 'FODIBM-R', 'parallelism': 'single GPU'},
-        'roofline': {'bound': 'hbm', 'kernel': 'grid sweep (collision + streaming + fluxes + energy)',
+        'roofline': {'bound': 'hbm', 'kernel': f'grid sweep, {args.sweep} (collision + streaming + fluxes + energy)',
                      'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
                      'frac': round(achieved / HBM_PEAK_GBS, 4),
                      'bytes_per_node': bytes_per_node, 'sweep_ms': round(sweep_ms, 5),

@@ -45,6 +45,7 @@ enum { LBM_IB_DIBM = 0, LBM_IB_FODIBM = 1, LBM_IB_FODIBM_R = 2 };
 enum { LBM_KERNEL_COS = 0, LBM_KERNEL_ROMA3 = 1 };
 enum { LBM_T_NONE = 0, LBM_T_DIRICHLET = 1, LBM_T_NEUMANN = 2 };
 enum { LBM_F32 = 32, LBM_F64 = 64 };
+enum { LBM_SWEEP_FUSED = 0, LBM_SWEEP_THREE_PASS = 1 };
 
 /* Problem parameters (lattice units). Sec. 2.1 (gas), Sec. 2.2 (solver), Sec. 3.4 (gamma). */
 typedef struct lbm_params {
@@ -55,7 +56,7 @@ typedef struct lbm_params {
     int kernel;         /* marker kernel: LBM_KERNEL_COS (Eq. (19), d = 2) or LBM_KERNEL_ROMA3 */
     int max_markers;    /* marker capacity reserved in the workspace */
     int with_aC;        /* 1: lattice third-order correction a^C in Eq. (A.9); 0: a^C = 0 */
-    int pad0;
+    int sweep;          /* LBM_SWEEP_FUSED (single pass, default) or LBM_SWEEP_THREE_PASS */
     double gamma;       /* ratio of specific heats */
     double mu;          /* dynamic viscosity (constant) */
     double lambda_;     /* thermal conductivity */

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -50,7 +51,7 @@ struct Dev {
     double *supp_w, *proj_w, *tw_w, *phi, *dbv, *W, *u_wall, *t_value, *G, *diag, *eps;
     int* t_kind;
     long long *rows, *row_ptr, *col_marker;
-    double *col_s, *fib, *fE, *h2off;
+    double *col_s, *fib, *fE, *h2off, *h2off2;   // sparse history, ping-pong with the state
 };
 
 int lattice_q(int dim) { return dim == 2 ? 9 : 19; }
@@ -102,6 +103,7 @@ size_t layout(const lbm_params& p, char* base, Dev* d) {
     o.fib = L.take<double>(sc * D);
     o.fE = L.take<double>(sc);
     o.h2off = L.take<double>(sc * (D == 3 ? 3 : 1));
+    o.h2off2 = L.take<double>(sc * (D == 3 ? 3 : 1));
     return align_up(L.off);
 }
 
@@ -121,6 +123,7 @@ struct lbm_handle {
     Geometry geom;
     std::vector<double> host_stage;
     int method = 0;
+    int chunk = 0;         // planes per workgroup of the fused sweep (0: per-lattice default)
     int markers_set = 0;
     int stepped = 0;       // a step has run since the body was set
     int any_step = 0;
@@ -177,7 +180,8 @@ void refresh_args(lbm_handle* h) {
     h->args.rows.rows = h->d.rows;
     h->args.rows.fib = h->d.fib;
     h->args.rows.fE = h->d.fE;
-    h->args.rows.h2off = h->d.h2off;
+    h->args.rows.h2off = h->cur == 0 ? h->d.h2off : h->d.h2off2;
+    h->args.rows.h2off_out = h->cur == 0 ? h->d.h2off2 : h->d.h2off;
     MarkersP& m = h->mk;
     m.m = h->geom.m;
     m.dim = h->D;
@@ -221,6 +225,7 @@ int validate_params(const lbm_params* p, std::string& why) {
     if (p->gamma <= 1.0 || p->mu <= 0.0 || p->lambda_ < 0.0 || p->rho_inf <= 0.0 || p->T_inf <= 0.0)
         return why = "need gamma > 1, mu > 0, lambda >= 0, rho_inf > 0, T_inf > 0", LBM_E_INVAL;
     if (p->sigma < 0.0 || p->sigma > 1.0) return why = "sigma must lie in [0, 1]", LBM_E_INVAL;
+    if (p->sweep != LBM_SWEEP_FUSED && p->sweep != LBM_SWEEP_THREE_PASS) return why = "bad sweep", LBM_E_INVAL;
     if (p->dim == 2 && p->u_inf[2] != 0.0) return why = "u_inf[2] must be 0 in 2D", LBM_E_INVAL;
     return LBM_OK;
 }
@@ -270,6 +275,7 @@ int lbm_init_grid(const lbm_params* p, void* ws, size_t bytes, void* stream, lbm
     h->Q = Q;
     h->N = (long long)p->nx * p->ny * p->nz;
     h->stream = (hipStream_t)stream;
+    if (const char* ch = std::getenv("LBMIB_FUSED_CHUNK")) h->chunk = std::atoi(ch);
     layout(*p, (char*)ws, &h->d);
 
     SweepArgs& a = h->args;
@@ -373,6 +379,7 @@ int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal, 
         HIPCHK(h, hipMemsetAsync(h->d.fib, 0, nr * D * 8, st));
         HIPCHK(h, hipMemsetAsync(h->d.fE, 0, nr * 8, st));
         HIPCHK(h, hipMemsetAsync(h->d.h2off, 0, nr * (D == 3 ? 3 : 1) * 8, st));
+        HIPCHK(h, hipMemsetAsync(h->d.h2off2, 0, nr * (D == 3 ? 3 : 1) * 8, st));
     }
     if (m) {
         HIPCHK(h, hipMemsetAsync(h->d.G, 0, (size_t)m * (D + 2) * 8, st));
@@ -409,7 +416,12 @@ int run_steps(lbm_handle* h, int n, hipEvent_t* ev) {
             if (r == hipSuccess && e4) r = hipEventRecord(e4[2], h->stream);
             ST* M = (ST*)h->d.work;
             ST* fcol = M + (size_t)(h->D + 2) * h->N;
-            if (r == hipSuccess) r = launch_split_step<LT, ST, ST>(h->args, A, B, M, fcol, h->stream);
+            if (r == hipSuccess) {
+                if (h->p.sweep == LBM_SWEEP_THREE_PASS)
+                    r = launch_split_step<LT, ST, ST>(h->args, A, B, M, fcol, h->stream);
+                else
+                    r = launch_fused_step<LT, ST>(h->args, A, B, h->chunk, h->stream);
+            }
             if (r == hipSuccess && e4) r = hipEventRecord(e4[3], h->stream);
             if (r == hipSuccess && last)
                 r = launch_residual<LT, ST>(h->args, A, B, h->d.partials, residual_parts(h->N), h->d.resid,
@@ -418,6 +430,7 @@ int run_steps(lbm_handle* h, int n, hipEvent_t* ev) {
         });
         if (e != hipSuccess) return fail(h, LBM_E_HIP, std::string("lbm_step: ") + hipGetErrorString(e));
         h->cur ^= 1;
+        refresh_args(h);
     }
     if (n > 0) {
         h->stepped = 1;
@@ -553,7 +566,10 @@ int lbm_set_fields(lbm_handle* h, int on_device, const double* rho, const double
     });
     if (e != hipSuccess) return fail(h, LBM_E_HIP, std::string("set_fields: ") + hipGetErrorString(e));
     const size_t nr = h->geom.rows.size();
-    if (nr) HIPCHK(h, hipMemsetAsync(h->d.h2off, 0, nr * (h->D == 3 ? 3 : 1) * 8, h->stream));
+    if (nr) {
+        HIPCHK(h, hipMemsetAsync(h->d.h2off, 0, nr * (h->D == 3 ? 3 : 1) * 8, h->stream));
+        HIPCHK(h, hipMemsetAsync(h->d.h2off2, 0, nr * (h->D == 3 ? 3 : 1) * 8, h->stream));
+    }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
 }
@@ -590,7 +606,9 @@ int lbm_set_state(lbm_handle* h, const double* f, const double* rhoE, const doub
         hipError_t e = dispatch(h, [&](auto L, auto S) {
             using LT = decltype(L);
             using ST = decltype(S);
-            return launch_import<LT, ST>(h->args, current<ST>(h), c, s, h->d.flag, h->stream);
+            SweepArgs ia = h->args;
+            ia.rows.h2off_out = const_cast<double*>(ia.rows.h2off);   // import writes the current buffer
+            return launch_import<LT, ST>(ia, current<ST>(h), c, s, h->d.flag, h->stream);
         });
         if (e != hipSuccess) return fail(h, LBM_E_HIP, std::string("set_state: ") + hipGetErrorString(e));
         HIPCHK(h, hipStreamSynchronize(h->stream));   // the host source must stay valid until copied

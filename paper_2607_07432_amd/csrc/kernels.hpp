@@ -29,7 +29,8 @@ struct RowsP {
     const long long* rows;  // [nrows] node of each row
     double* fib;            // [D][nrows] momentum forcing
     double* fE;             // [nrows] energy forcing w + q
-    double* h2off;          // [NOFF][nrows] off-diagonal force history (xy[, xz, yz])
+    const double* h2off;    // [NOFF][nrows] off-diagonal force history (xy[, xz, yz]), current step
+    double* h2off_out;      // the same for the next step (ping-pong with h2off)
 };
 
 struct FreeStream {
@@ -67,6 +68,9 @@ struct MarkersP {
 // Split sweep (macros -> collide -> stream + fluxes + energy).
 template <class L, class S, class C>
 hipError_t launch_split_step(const SweepArgs& a, StateP<S> A, StateP<S> B, C* M, C* fcol, hipStream_t st);
+
+template <class L, class S>
+hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, hipStream_t st);
 
 template <class L, class S>
 hipError_t launch_init_state(const SweepArgs& a, StateP<S> A, hipStream_t st);

@@ -87,30 +87,6 @@ __host__ __device__ __forceinline__ void feq_dev(C rho, const C* u, C theta, C* 
     }
 }
 
-// Eq. (A.4): w_i [H2_i : Pi / (2 cs^4) + sum_k H3r_ik Pi3r_k / N_k].
-template <class L, class C>
-__device__ __forceinline__ void fneq_of(const C (*Pi)[3], const C* u, C* fneq) {
-    constexpr int D = L::D;
-    C p3[L::K3];
-    pi3r_of<L, C>(u, Pi, p3);
-    C tr = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) tr += Pi[a][a];
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        C s = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int b = 0; b < D; ++b)
-                if (L::c[i][a] * L::c[i][b] != 0) s += C(L::c[i][a] * L::c[i][b]) * Pi[a][b];
-        C h = 0;
-#pragma unroll
-        for (int k = 0; k < L::K3; ++k) h += C(h3r<L>(i, k) / h3r_norm<L>(k)) * p3[k];
-        fneq[i] = C(L::w[i]) * (C(4.5) * (s - C(CS2) * tr) + h);
-    }
-}
-
 // Neighbour data the collision at a node needs (central differences, Eq. (A.9)).
 template <class C>
 struct Stencil {
@@ -124,12 +100,23 @@ struct Stencil {
 // H2 = dev(a^F) (the deviatoric sum_i (c c - delta c^2/D) F_i, Eq. (A.7)).
 // fd: population deviations at the node; H2: previous history (full symmetric
 // tensor, H2[a][b]); fib: momentum forcing of the node.
+//
+// f^col = f^eq + (1 - 1/taubar) f^neq + F/2 is a Hermite series of order 3 in every
+// term (Eqs. (A.3), (A.4), (7)), so the three are summed coefficient by coefficient and
+// reconstructed once per population:
+//   f^col_i - w_i = w_i [ (rho - 1) + r_i rho (theta - 1) + 3 c_i . J
+//                         + 9/2 (c_i c_i : A - cs^2 tr A) + sum_k H3r_ik B_k / N_k ],
+//   J = rho u + f/2,  A = rho u u + (1 - 1/taubar) Pi + a^F/2,
+//   B = (rho u u u)^(3r) + (1 - 1/taubar) Pi^(3r).
+// The population part of Pi (Eq. (A.7)) uses the exact lattice moment
+// sum_i c c (f^eq_i - w_i) = rho u u + (rho theta - 1) cs^2 I, whose deviatoric part is dev(rho u u).
 template <class L, class C>
 __device__ __forceinline__ void collide(const Gas& g, const C* fd, const Node<L, C>& n, const Stencil<C>& s,
                                         const C* fib, const C (*H2)[3], C* fcol, C (*H2new)[3]) {
     constexpr int D = L::D;
     const C rho = n.rho;
     const C theta = n.T;
+    const C* u = n.u;
     C div = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) div += s.du[a][a];
@@ -137,77 +124,100 @@ __device__ __forceinline__ void collide(const Gas& g, const C* fd, const Node<L,
     // Eq. (A.9). d/dt[rho(1 - theta)] from the Euler balance laws:
     //   d rho/dt = -div(rho u),  d(rho theta)/dt = -u.grad(rho theta) - gamma rho theta div u.
     const C dgdt = -s.div_rhou + s.u_grad_p + C(g.gamma) * rho * theta * div;
+    const C iso = C(2.0 / D) * rho * C(CS2) * div - C(CS2) * dgdt;
     C aF[3][3];
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = 0; b < D; ++b) {
-            C v = fib[a] * n.u[b] + fib[b] * n.u[a];
+        for (int b = a; b < D; ++b) {
+            C v = fib[a] * u[b] + fib[b] * u[a];
             if (a == b) {
-                v += C(2.0 / D) * rho * C(CS2) * div - C(CS2) * dgdt;
+                v += iso;
                 if (g.with_aC) v -= s.dmu3[a];
             }
             aF[a][b] = v;
+            aF[b][a] = v;
         }
+    C tra = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) tra += aF[a][a];
 
-    C feqd[L::Q];
-    feq_dev<L, C>(rho, n.u, theta, feqd);
-
-    // Eq. (A.7): Pi = sigma [sum_i dev(cc) (f_i - f^eq_i) + H2/2] - (1 - sigma) rho cs^2 taubar S.
-    const C taubar = C(g.mu) / (rho * C(CS2)) + C(0.5);   // tau = nu / cs^2, Eq. (6)
-    C m2[3][3];
+    // Second moment of the populations.
+    C M2[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) m2[a][b] = 0;
+        for (int b = 0; b < 3; ++b) M2[a][b] = 0;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const C gi = fd[i] - feqd[i];
+    for (int i = 0; i < L::Q; ++i)
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
             for (int b = a; b < D; ++b)
-                if (L::c[i][a] * L::c[i][b] != 0) m2[a][b] += C(L::c[i][a] * L::c[i][b]) * gi;
-    }
-    C trm = 0;
+                if (L::c[i][a] * L::c[i][b] != 0) M2[a][b] += C(L::c[i][a] * L::c[i][b]) * fd[i];
+
+    // Eq. (A.7): Pi = sigma [dev(M2) - dev(rho u u) + H2/2] - (1 - sigma) rho cs^2 taubar S.
+    const C taubar = C(g.mu) / (rho * C(CS2)) + C(0.5);   // tau = nu / cs^2, Eq. (6)
+    const C om = C(1) - C(1) / taubar;
+    C trP = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) trm += m2[a][a];
+    for (int a = 0; a < D; ++a) trP += M2[a][a] - rho * u[a] * u[a];
     const C sig = C(g.sigma);
     const C fdc = (C(1) - sig) * rho * C(CS2) * taubar;
     C Pi[3][3];
 #pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Pi[a][b] = 0;
+#pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = a; b < D; ++b) {
-            C pop = m2[a][b] + C(0.5) * H2[a][b];
+            C pop = M2[a][b] - rho * u[a] * u[b] + C(0.5) * H2[a][b];
             C S = s.du[a][b] + s.du[b][a];
             if (a == b) {
-                pop -= trm / C(D);
+                pop -= trP / C(D);
                 S -= C(2.0 / D) * div;
             }
             Pi[a][b] = sig * pop - fdc * S;
             Pi[b][a] = Pi[a][b];
         }
-    C fneq[L::Q];
-    fneq_of<L, C>(Pi, n.u, fneq);
 
-    // Eq. (7): F_i = w_i [c_i . f / cs^2 + H2_i : a^F / (2 cs^4)].
-    C tra = 0;
+    // Combined Hermite coefficients.
+    C J[3], A[3][3];
 #pragma unroll
-    for (int a = 0; a < D; ++a) tra += aF[a][a];
-    const C om = C(1) - C(1) / taubar;
+    for (int a = 0; a < D; ++a) J[a] = rho * u[a] + C(0.5) * fib[a];
+    C trA = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a; b < D; ++b) {
+            A[a][b] = rho * u[a] * u[b] + om * Pi[a][b] + C(0.5) * aF[a][b];
+            if (a == b) trA += A[a][a];
+        }
+    C B3[L::K3], P3[L::K3];
+    a3r_of_uuu<L, C>(u, rho, B3);
+    pi3r_of<L, C>(u, Pi, P3);
+#pragma unroll
+    for (int k = 0; k < L::K3; ++k) B3[k] += om * P3[k];
+    const C base = (rho - C(1));
+    const C rtm1 = rho * (theta - C(1));
+    const C iso2 = C(CS2) * trA;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        C cf = 0, cac = 0;
+        C cJ = 0, ccA = 0, h = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            cf += C(L::c[i][a]) * fib[a];
+            if (L::c[i][a]) cJ += C(L::c[i][a]) * J[a];
 #pragma unroll
-            for (int b = 0; b < D; ++b)
-                if (L::c[i][a] * L::c[i][b] != 0) cac += C(L::c[i][a] * L::c[i][b]) * aF[a][b];
+            for (int b = a; b < D; ++b)
+                if (L::c[i][a] * L::c[i][b] != 0) ccA += C((a == b ? 1 : 2) * L::c[i][a] * L::c[i][b]) * A[a][b];
         }
-        const C Fi = C(L::w[i]) * (C(3) * cf + C(4.5) * (cac - C(CS2) * tra));
-        fcol[i] = feqd[i] + om * fneq[i] + C(0.5) * Fi;
+#pragma unroll
+        for (int k = 0; k < L::K3; ++k)
+            if (h3r<L>(i, k) != 0.0) h += C(h3r<L>(i, k) / h3r_norm<L>(k)) * B3[k];
+        const C rest = C((L::w[i] - (i == 0 ? 1.0 : 0.0)) / L::w[i]);
+        fcol[i] = C(L::w[i]) * (base + rest * rtm1 + C(3) * cJ + C(4.5) * (ccA - iso2) + h);
     }
 #pragma unroll
     for (int a = 0; a < D; ++a)
@@ -215,11 +225,9 @@ __device__ __forceinline__ void collide(const Gas& g, const C* fd, const Node<L,
         for (int b = 0; b < D; ++b) H2new[a][b] = aF[a][b] - (a == b ? tra / C(D) : C(0));
 }
 
-// MUSCL-Hancock face value on the face between cells a and b = a + e (Eqs. (A.14)-(A.16)),
-// from Phi at cells a-1, a, b, b+1 and the face-normal velocity at a and b.
-// Velocities below U_ZERO count as zero in both sign decisions (sign(u) in eta and the
-// upwind test): the operator is discontinuous at u = 0 and a velocity that vanishes by
-// symmetry is a rounding residue of either sign.
+// Velocities below U_ZERO count as zero in both sign decisions of the MUSCL operator
+// (sign(u) in eta and the upwind test): the operator is discontinuous at u = 0 and a
+// velocity that vanishes by symmetry is a rounding residue of either sign.
 constexpr double U_ZERO = 1e-7;
 
 template <class C>
@@ -227,55 +235,76 @@ __device__ __forceinline__ C sgn(C v) {
     return C((v > C(U_ZERO)) - (v < C(-U_ZERO)));
 }
 
-template <class C>
-__device__ __forceinline__ C muscl(C pm, C pa, C pb, C pp, C ua, C ub) {
-    const C ut = C(0.5) * (ua + ub);
-    if (ut >= C(-U_ZERO)) {
-        const C eta = (C(2) * ua - sgn(ua)) / C(3);
-        const C slope = C(0.5) * ((C(1) + eta) * (pa - pm) + (C(1) - eta) * (pb - pa));
-        return pa + C(0.5) * slope * (C(1) - ua);
-    }
-    const C eta = (C(2) * ub - sgn(ub)) / C(3);
-    const C slope = C(0.5) * ((C(1) + eta) * (pb - pa) + (C(1) - eta) * (pp - pb));
-    return pb - C(0.5) * slope * (C(1) + ub);
-}
-
-// Cell quantities of the energy flux. p' = p - cs^2 keeps the pressure as a deviation
-// (the lattice-weight part of the LB momentum flux is cs^2 delta_ab exactly).
+// Cell quantities of the energy flux.
 template <class L, class C>
 struct Cell {
     C rho, u[3], T;
 };
 
-// Energy flux through the face between cells A (index 1 of the 4-cell stencil) and B
-// (index 2) along axis a (Eq. (11)), given the LB mass flux Fr and deviation momentum
-// fluxes Fm[b] (lattice-weight part removed) through that face.
+// MUSCL-Hancock face value on the face between cells 1 and 2 of a 4-cell stencil
+// (Eqs. (A.14)-(A.16)) is linear in Phi for given face-normal velocities:
+//   F*(Phi) = sum_t w_t Phi_t. Left state (u~ >= 0): s = (1 - u_1)/4,
+//   w = (-s (1 + eta_1), 1 + 2 s eta_1, s (1 - eta_1), 0); right state: s = (1 + u_2)/4,
+//   w = (0, s (1 + eta_2), 1 - 2 s eta_2, -s (1 - eta_2)); eta = (2 u - sign(u))/3.
+template <class C>
+__device__ __forceinline__ void muscl_weights(C ua, C ub, C* w) {
+    if (C(0.5) * (ua + ub) >= C(-U_ZERO)) {
+        const C eta = (C(2) * ua - sgn(ua)) / C(3);
+        const C s = (C(1) - ua) * C(0.25);
+        w[0] = -s * (C(1) + eta);
+        w[1] = C(1) + C(2) * s * eta;
+        w[2] = s * (C(1) - eta);
+        w[3] = 0;
+    } else {
+        const C eta = (C(2) * ub - sgn(ub)) / C(3);
+        const C s = (C(1) + ub) * C(0.25);
+        w[0] = 0;
+        w[1] = s * (C(1) + eta);
+        w[2] = C(1) - C(2) * s * eta;
+        w[3] = -s * (C(1) - eta);
+    }
+}
+
+// Energy flux through the face between cells 1 and 2 of the 4-cell stencil c4 along axis a
+// (Eq. (11)), given the LB mass flux Fr and momentum fluxes Fm[b] (lattice-weight part
+// cs^2 delta_ab removed) through that face:
+//   F = F*(rho H u_a) + (h - k)_f [Fr - F*(rho u_a)] + sum_b u_b,f [Fm_b - F*(rho u_a u_b + p' delta_ab)]
+//       - lambda (T_2 - T_1),
+// with p' = p - cs^2, H = k + Cp T, h = Cp T, k = |u|^2/2, (.)_f the mean of cells 1 and 2.
+// By linearity of F* this is F*(Psi) + (h - k)_f Fr + sum_b u_b,f Fm_b - lambda (T_2 - T_1),
+// Psi = rho u_a (k + Cp T) - (h - k)_f rho u_a - sum_b u_b,f rho u_a u_b - u_a,f p'.
 template <class L, class C>
 __device__ __forceinline__ C energy_flux(const Gas& g, int a, const Cell<L, C>* c4, C Fr, const C* Fm) {
     constexpr int D = L::D;
-    C phiH[4], phiM[4], k[4], pd[4];
+    C k[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         C uu = 0;
 #pragma unroll
         for (int b = 0; b < D; ++b) uu += c4[t].u[b] * c4[t].u[b];
         k[t] = C(0.5) * uu;
-        pd[t] = (c4[t].rho * c4[t].T - C(1)) * C(CS2);        // p - cs^2
-        phiH[t] = c4[t].rho * (k[t] + C(g.Cp) * c4[t].T) * c4[t].u[a];
-        phiM[t] = c4[t].rho * c4[t].u[a];
     }
-    const C ua = c4[1].u[a], ub = c4[2].u[a];
-    C flux = muscl(phiH[0], phiH[1], phiH[2], phiH[3], ua, ub);
-    const C hk = C(0.5) * ((C(g.Cp) * c4[1].T - k[1]) + (C(g.Cp) * c4[2].T - k[2]));
-    flux += hk * (Fr - muscl(phiM[0], phiM[1], phiM[2], phiM[3], ua, ub));
+    const C Cp = C(g.Cp);
+    const C hk = C(0.5) * ((Cp * c4[1].T - k[1]) + (Cp * c4[2].T - k[2]));
+    C ubf[3];
 #pragma unroll
-    for (int b = 0; b < D; ++b) {
-        C ph[4];
+    for (int b = 0; b < D; ++b) ubf[b] = C(0.5) * (c4[1].u[b] + c4[2].u[b]);
+    C w[4];
+    muscl_weights<C>(c4[1].u[a], c4[2].u[a], w);
+    C fs = 0;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) ph[t] = c4[t].rho * c4[t].u[a] * c4[t].u[b] + (a == b ? pd[t] : C(0));
-        const C ubf = C(0.5) * (c4[1].u[b] + c4[2].u[b]);
-        flux += ubf * (Fm[b] - muscl(ph[0], ph[1], ph[2], ph[3], ua, ub));
+    for (int t = 0; t < 4; ++t) {
+        const C ru = c4[t].rho * c4[t].u[a];
+        C ub_u = 0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) ub_u += ubf[b] * c4[t].u[b];
+        const C pd = (c4[t].rho * c4[t].T - C(1)) * C(CS2);
+        const C psi = ru * (k[t] + Cp * c4[t].T - hk - ub_u) - ubf[a] * pd;
+        fs += w[t] * psi;
     }
+    C flux = fs + hk * Fr;
+#pragma unroll
+    for (int b = 0; b < D; ++b) flux += ubf[b] * Fm[b];
     flux -= C(g.lambda_) * (c4[2].T - c4[1].T);
     return flux;
 }

@@ -1,0 +1,492 @@
+// Fused single-pass grid sweep: collision, pull streaming, LB face fluxes, MUSCL-Hancock
+// energy flux and the rho E update of one time step in one kernel (Eqs. (6), (7), (10),
+// (11), (A.3)-(A.16)); every node update reads and writes the state once.
+//
+// A workgroup owns a TX x TY tile of the plane normal to the marching axis (z in 3D,
+// y in 2D) and marches along that axis over a chunk of planes. Three rings live in LDS:
+//   mac  : predicted macros (rho, half-force velocity, T) of 3 planes on the tile + 2 halo;
+//   fcA  : post-collision populations moving +1 along the marching axis, 3 planes, tile + 1;
+//   fcB  : the other post-collision populations, 2 planes, tile + 1.
+// Per output plane p: (a) macros of plane p+2, (b) collision of plane p+1 (needs macros of
+// p..p+2 for the velocity gradients), (c) output of plane p: pull streaming from planes
+// p-1..p+1, face fluxes of the +x/+y faces (shared through LDS) and of the p+1/2 face
+// (the p-1/2 face is carried in a register from the previous plane).
+// Only the in-plane halo is recomputed; along the marching axis each plane is computed
+// once per chunk (plus a 2-plane warm-up).
+#include "kernels.hpp"
+
+namespace lbmib {
+
+namespace {
+
+// Marching-axis component of population i and its slot in the two rings.
+template <class L>
+__host__ __device__ constexpr int cm(int i) {
+    return L::c[i][L::D - 1];
+}
+template <class L>
+__host__ __device__ constexpr int count_up() {
+    int n = 0;
+    for (int i = 0; i < L::Q; ++i) n += cm<L>(i) == 1;
+    return n;
+}
+template <class L>
+__host__ __device__ constexpr int slot_of(int i) {
+    int n = 0;
+    const bool up = cm<L>(i) == 1;
+    for (int j = 0; j < i; ++j) n += (cm<L>(j) == 1) == up;
+    return n;
+}
+
+__device__ __forceinline__ int wrapm(int v, int n) {
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Periodic index for |v| < 2n (grids at least a tile plus its halo wide).
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+template <class L, int TX, int TY>
+struct FG {
+    static constexpr int D = L::D;
+    static constexpr int W1 = TX + 2, H1 = D == 3 ? TY + 2 : 1;
+    static constexpr int T = W1 * H1;               // one thread per node of the tile + 1 halo
+    static constexpr int W2 = TX + 4, H2 = D == 3 ? TY + 4 : 1;
+    static constexpr int N1 = W1 * H1, N2 = W2 * H2;
+    static constexpr int OY = D == 3 ? 1 : 0;      // y offset of R1 inside R2 (and of the tile inside R1)
+    static constexpr int NA = count_up<L>(), NB = L::Q - count_up<L>();
+    static constexpr int NM = D + 2;                // rho, u[D], T
+    static constexpr int MA = D - 1;                // marching axis
+};
+
+template <class L, class S, class C, int TX, int TY>
+struct FusedSmem {
+    using G = FG<L, TX, TY>;
+    C mac[3][G::NM][G::N2];
+    C fcA[3][G::NA][G::N1];
+    C fcB[2][G::NB][G::N1];
+    C fex[TY][TX + 1];
+    C fey[G::D == 3 ? TY + 1 : 1][TX];
+};
+
+struct FusedArgs {
+    int tiles_x, tiles_y, chunks, chunk, total, per_xcd;
+    int small;      // a grid dimension is smaller than a tile plus halo: use the general modulo
+};
+
+}  // namespace
+
+template <class L, class S, class C, int TX, int TY>
+__global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(SweepArgs a, FusedArgs fa, StateP<S> A, StateP<S> B) {
+    using G = FG<L, TX, TY>;
+    constexpr int D = L::D;
+    __shared__ FusedSmem<L, S, C, TX, TY> sm;
+
+    const GridP& g = a.grid;
+    const long long N = g.N;
+    const int nm = D == 3 ? g.nz : g.ny;               // length of the marching axis
+    // XCD-aware placement: consecutive logical workgroups (neighbouring tiles) share an XCD.
+    const int w = blockIdx.x;
+    const int logical = (w % 8) * fa.per_xcd + w / 8;
+    if (logical >= fa.total) return;
+    const int per_plane = fa.tiles_x * fa.tiles_y;
+    const int chunk = logical / per_plane;
+    const int rem = logical % per_plane;
+    const int x0 = (rem % fa.tiles_x) * TX;
+    const int y0 = D == 3 ? (rem / fa.tiles_x) * TY : 0;
+    const int z0 = chunk * fa.chunk;
+    const int z1 = min(z0 + fa.chunk, nm);
+    const int t = threadIdx.x;
+
+    const bool small = fa.small != 0;
+    auto wr = [&](int v, int n) { return small ? wrapm(v, n) : wrap1(v, n); };
+    auto gnode = [&](int x, int y, int m) -> long long {
+        const int xw = wr(x, g.nx);
+        if (D == 3) return (long long)xw + (long long)g.nx * ((long long)wr(y, g.ny) + (long long)g.ny * wr(m, nm));
+        return (long long)xw + (long long)g.nx * wr(m, nm);
+    };
+    auto s3 = [](int q) { return (q + 6) % 3; };
+    auto s2 = [](int q) { return (q + 6) % 2; };
+
+    // ---- (a) predicted macros of plane q on the tile + 2 halo. The global loads are split
+    // from the arithmetic so that they can be issued one stage ahead (prefetch).
+    constexpr int KA = (G::N2 + G::T - 1) / G::T;
+    S pa_f[KA][L::Q];
+    S pa_e[KA];
+    int pa_r[KA];
+    auto load_macros = [&](int q) {
+#pragma unroll
+        for (int kk = 0; kk < KA; ++kk) {
+            const int k = t + kk * G::T;
+            if (k >= G::N2) break;
+            const int jx = k % G::W2, jy = k / G::W2;
+            const long long n = gnode(x0 - 2 + jx, y0 - 2 * G::OY + jy, q);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) pa_f[kk][i] = A.f[i * N + n];
+            pa_e[kk] = A.e[n];
+            pa_r[kk] = a.rows.rowmap[n];
+        }
+    };
+    auto compute_macros = [&](int q) {
+        const int sl = s3(q);
+#pragma unroll
+        for (int kk = 0; kk < KA; ++kk) {
+            const int k = t + kk * G::T;
+            if (k >= G::N2) break;
+            C drho = 0, j[3] = {0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                const C f = C(pa_f[kk][i]);
+                drho += f;
+#pragma unroll
+                for (int b = 0; b < D; ++b)
+                    if (L::c[i][b]) j[b] += C(L::c[i][b]) * f;
+            }
+            const C rho = C(1) + drho;
+            C uu = 0;
+#pragma unroll
+            for (int b = 0; b < D; ++b) uu += (j[b] / rho) * (j[b] / rho);
+            const C T = ((C(pa_e[kk]) + C(a.fs.e_ref)) / rho - C(0.5) * uu) / C(a.gas.Cv);
+            const int r = pa_r[kk];
+            sm.mac[sl][0][k] = rho;
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const C fib = r >= 0 ? C(a.rows.fib[(long long)b * a.rows.nrows + r]) : C(0);
+                sm.mac[sl][1 + b][k] = (j[b] + C(0.5) * fib) / rho;
+            }
+            sm.mac[sl][1 + D][k] = T;
+        }
+    };
+
+    auto mcell = [&](int sl, int k2) {
+        Cell<L, C> c;
+        c.rho = sm.mac[sl][0][k2];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) c.u[b] = b < D ? sm.mac[sl][1 + b][k2] : C(0);
+        c.T = sm.mac[sl][1 + D][k2];
+        return c;
+    };
+
+    // ---- (b) collision of plane q on the tile + 1 halo (one node per thread)
+    S pb_f[L::Q];
+    S pb_h[2];
+    int pb_r;
+    auto load_collide = [&](int q) {
+        const int jx = t % G::W1, jy = t / G::W1;
+        const long long n = gnode(x0 - 1 + jx, y0 - G::OY + jy, q);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) pb_f[i] = A.f[i * N + n];
+        pb_h[0] = A.h2[n];
+        pb_h[1] = D == 3 ? A.h2[N + n] : S(0);
+        pb_r = a.rows.rowmap[n];
+    };
+    auto compute_collide = [&](int q) {
+        const int sl = s3(q), slm = s3(q - 1), slp = s3(q + 1);
+        const int sa = s3(q), sb = s2(q);
+        {
+            const int k = t;
+            const int jx = k % G::W1, jy = k / G::W1;
+            const int k2 = (jx + 1) + G::W2 * (jy + G::OY);
+            const int xu = x0 - 1 + jx, yu = y0 - G::OY + jy;
+            const long long n = gnode(xu, yu, q);
+            C fd[L::Q];
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) fd[i] = C(pb_f[i]);
+            const Cell<L, C> c0 = mcell(sl, k2);
+            Node<L, C> nd;
+            nd.rho = c0.rho;
+            nd.T = c0.T;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) nd.u[b] = c0.u[b];
+            Stencil<C> st;
+            st.div_rhou = 0;
+            st.u_grad_p = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                st.dmu3[b] = 0;
+#pragma unroll
+                for (int qq = 0; qq < 3; ++qq) st.du[qq][b] = 0;
+            }
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                Cell<L, C> cp, cmn;
+                if (b == G::MA) {
+                    cp = mcell(slp, k2);
+                    cmn = mcell(slm, k2);
+                } else {
+                    const int stride = b == 0 ? 1 : G::W2;
+                    cp = mcell(sl, k2 + stride);
+                    cmn = mcell(sl, k2 - stride);
+                }
+#pragma unroll
+                for (int qq = 0; qq < D; ++qq) st.du[qq][b] = C(0.5) * (cp.u[qq] - cmn.u[qq]);
+                st.div_rhou += C(0.5) * (cp.rho * cp.u[b] - cmn.rho * cmn.u[b]);
+                st.u_grad_p += nd.u[b] * C(0.5) * (cp.rho * cp.T - cmn.rho * cmn.T);
+                st.dmu3[b] = C(0.5) * (cp.rho * cp.u[b] * cp.u[b] * cp.u[b] - cmn.rho * cmn.u[b] * cmn.u[b] * cmn.u[b]);
+            }
+            C H2[3][3];
+            H2[0][0] = C(pb_h[0]);
+            if (D == 3) {
+                H2[1][1] = C(pb_h[1]);
+                H2[2][2] = -(H2[0][0] + H2[1][1]);
+            } else {
+                H2[1][1] = -H2[0][0];
+            }
+            const int r = pb_r;
+            const int nr = a.rows.nrows;
+            C fib[3] = {0, 0, 0}, off[3] = {0, 0, 0};
+            if (r >= 0) {
+#pragma unroll
+                for (int b = 0; b < D; ++b) fib[b] = C(a.rows.fib[(long long)b * nr + r]);
+#pragma unroll
+                for (int kk = 0; kk < L::NOFF; ++kk) off[kk] = C(a.rows.h2off[(long long)kk * nr + r]);
+            }
+            H2[0][1] = H2[1][0] = off[0];
+            if (D == 3) {
+                H2[0][2] = H2[2][0] = off[1];
+                H2[1][2] = H2[2][1] = off[2];
+            }
+            C fc[L::Q];
+            C H2n[3][3];
+            collide<L, C>(a.gas, fd, nd, st, fib, H2, fc, H2n);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                if (cm<L>(i) == 1)
+                    sm.fcA[sa][slot_of<L>(i)][k] = fc[i];
+                else
+                    sm.fcB[sb][slot_of<L>(i)][k] = fc[i];
+            }
+            // Tile nodes (not halo, not beyond the grid) write the new history.
+            const bool tile = jx >= 1 && jx <= TX && (D == 2 || (jy >= 1 && jy <= TY)) && xu < g.nx &&
+                              (D == 2 || yu < g.ny);
+            if (tile) {
+                if (r >= 0) {
+                    a.rows.h2off_out[r] = H2n[0][1];
+                    if (D == 3) {
+                        a.rows.h2off_out[(long long)nr + r] = H2n[0][2];
+                        a.rows.h2off_out[2LL * nr + r] = H2n[1][2];
+                    }
+                }
+                int copies = 1;
+                bool write = true;
+                if (g.bc_x == 1) {
+                    if (xu < 2) {
+                        B.h2[n] = S(0);
+                        if (D == 3) B.h2[N + n] = S(0);
+                        write = false;
+                    } else if (xu >= g.nx - 2) {
+                        write = false;
+                    } else if (xu == g.nx - 3) {
+                        copies = 3;
+                    }
+                }
+                if (write)
+                    for (int c = 0; c < copies; ++c) {
+                        B.h2[n + c] = S(H2n[0][0]);
+                        if (D == 3) B.h2[N + n + c] = S(H2n[1][1]);
+                    }
+            }
+        }
+    };
+
+    // Post-collision population i at R1 coords (jx, jy) of plane q.
+    auto fcr = [&](int i, int jx, int jy, int q) -> C {
+        const int k = jx + G::W1 * jy;
+        if (cm<L>(i) == 1) return sm.fcA[s3(q)][slot_of<L>(i)][k];
+        return sm.fcB[s2(q)][slot_of<L>(i)][k];
+    };
+
+    // LB mass and momentum (lattice-weight part removed) flux through the face base + e_ax/2,
+    // base at R1 coords (bx, by) of plane q; ax is a physical axis (Eqs. (A.11)-(A.13)).
+    auto lb_flux = [&](int ax, int bx, int by, int q, C& Fr, C* Fm) {
+        Fr = 0;
+        Fm[0] = Fm[1] = Fm[2] = 0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const int ci = L::c[i][ax];
+            if (ci == 0) continue;
+            const int cx = L::c[i][0], cy = D == 3 ? L::c[i][1] : 0, cmi = cm<L>(i);
+            C v;
+            if (ax == G::MA) {
+                if (ci == 1)
+                    v = C(0.5) * (fcr(i, bx, by, q) + fcr(i, bx - cx, by - cy, q));
+                else
+                    v = -C(0.5) * (fcr(i, bx, by, q + 1) + fcr(i, bx - cx, by - cy, q + 1));
+            } else {
+                const int ex = ax == 0, ey = ax == 1;
+                if (ci == 1)
+                    v = C(0.5) * (fcr(i, bx, by, q) + fcr(i, bx + ex - cx, by + ey - cy, q - cmi));
+                else
+                    v = -C(0.5) * (fcr(i, bx + ex, by + ey, q) + fcr(i, bx - cx, by - cy, q - cmi));
+            }
+            Fr += v;
+#pragma unroll
+            for (int b = 0; b < D; ++b)
+                if (L::c[i][b]) Fm[b] += C(L::c[i][b]) * v;
+        }
+    };
+
+    // In-plane energy flux through the face base + e_ax/2 (base at R1 coords), plane q.
+    auto inplane_flux = [&](int ax, int bx, int by, int q) -> C {
+        C Fr, Fm[3];
+        lb_flux(ax, bx, by, q, Fr, Fm);
+        const int sl = s3(q);
+        const int k2 = (bx + 1) + G::W2 * (by + G::OY);
+        const int stride = ax == 0 ? 1 : G::W2;
+        Cell<L, C> c4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c4[u] = mcell(sl, k2 + (u - 1) * stride);
+        return energy_flux<L, C>(a.gas, ax, c4, Fr, Fm);
+    };
+
+    // Node of this thread in the tile + 1 halo (R1 coords); interior threads own an output node.
+    const int jx1 = t % G::W1, jy1 = D == 3 ? t / G::W1 : 0;
+    const bool own_out = jx1 >= 1 && jx1 <= TX && (D == 2 || (jy1 >= 1 && jy1 <= TY));
+    const bool own_fx = jx1 <= TX && (D == 2 || (jy1 >= 1 && jy1 <= TY));      // face base + e_x/2
+    const bool own_fy = D == 3 && jx1 >= 1 && jx1 <= TX && jy1 <= TY;          // face base + e_y/2
+    const int bx1 = jx1, by1 = jy1;
+    const int k2own = (jx1 + 1) + G::W2 * (jy1 + G::OY);                        // R2 coords
+    const int xo = x0 - 1 + jx1, yo = y0 - G::OY + jy1;
+    const bool real = own_out && xo < g.nx && (D == 2 || yo < g.ny);
+    const int frow = D == 3 ? jy1 - 1 : 0;
+
+    // ---- prologue: macros of z0-2 .. z0, collision of z0-1, macros of z0+1, collision of z0
+    load_macros(z0 - 2);
+    compute_macros(z0 - 2);
+    load_macros(z0 - 1);
+    compute_macros(z0 - 1);
+    load_macros(z0);
+    compute_macros(z0);
+    __syncthreads();
+    load_collide(z0 - 1);
+    compute_collide(z0 - 1);
+    __syncthreads();
+    Cell<L, C> cm2 = mcell(s3(z0 - 2), k2own);
+    Cell<L, C> prev = mcell(s3(z0 - 1), k2own);   // own column, plane p - 1
+    __syncthreads();
+    load_macros(z0 + 1);
+    compute_macros(z0 + 1);
+    __syncthreads();
+    load_collide(z0);
+    compute_collide(z0);
+    __syncthreads();
+    C fm_prev = 0;                                  // energy flux through the p - 1/2 face
+    if (own_out) {
+        C Fr, Fm[3];
+        lb_flux(G::MA, bx1, by1, z0 - 1, Fr, Fm);
+        Cell<L, C> c4[4] = {cm2, prev, mcell(s3(z0), k2own), mcell(s3(z0 + 1), k2own)};
+        fm_prev = energy_flux<L, C>(a.gas, G::MA, c4, Fr, Fm);
+    }
+    load_macros(z0 + 2);
+    load_collide(z0 + 1);
+
+    for (int p = z0; p < z1; ++p) {
+        compute_macros(p + 2);
+        __syncthreads();
+        compute_collide(p + 1);
+        __syncthreads();
+        // Issue the next plane's global loads now; they complete while plane p is output.
+        if (p + 1 < z1) {
+            load_macros(p + 3);
+            load_collide(p + 2);
+        }
+
+        // ---- (c) output plane p
+        C fnew[L::Q];
+        if (own_out) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                fnew[i] = fcr(i, bx1 - L::c[i][0], by1 - (D == 3 ? L::c[i][1] : 0), p - cm<L>(i));
+        }
+        if (own_fx) sm.fex[frow][jx1] = inplane_flux(0, bx1, by1, p);
+        if (D == 3 && own_fy) sm.fey[jy1][jx1 - 1] = inplane_flux(1, bx1, by1, p);
+        C fm_now = 0;
+        if (own_out) {
+            C Fr, Fm[3];
+            lb_flux(G::MA, bx1, by1, p, Fr, Fm);
+            const Cell<L, C> cp0 = mcell(s3(p), k2own);
+            Cell<L, C> c4[4] = {prev, cp0, mcell(s3(p + 1), k2own), mcell(s3(p + 2), k2own)};
+            fm_now = energy_flux<L, C>(a.gas, G::MA, c4, Fr, Fm);
+            prev = cp0;
+        }
+        __syncthreads();
+        C ediv = 0;
+        if (own_out) {
+            ediv = (sm.fex[frow][jx1] - sm.fex[frow][jx1 - 1]) + (fm_now - fm_prev);
+            if (D == 3) ediv += sm.fey[jy1][jx1 - 1] - sm.fey[jy1 - 1][jx1 - 1];
+        }
+        fm_prev = fm_now;
+        if (!real) continue;
+        const long long n = gnode(xo, yo, p);
+        if (g.bc_x == 1) {
+            if (xo < 2) {
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i) B.f[i * N + n] = S(a.fs.fdev[i]);
+                B.e[n] = S(0);
+                continue;
+            }
+            if (xo >= g.nx - 2) continue;
+        }
+        const int r = a.rows.rowmap[n];
+        const C fE = r >= 0 ? C(a.rows.fE[r]) : C(0);
+        const C enew = C(A.e[n]) - ediv + fE;
+        const int copies = (g.bc_x == 1 && xo == g.nx - 3) ? 3 : 1;
+        for (int c = 0; c < copies; ++c) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) B.f[i * N + n + c] = S(fnew[i]);
+            B.e[n + c] = S(enew);
+        }
+    }
+}
+
+namespace {
+
+template <class L, class S>
+struct Tile;
+template <>
+struct Tile<D3Q19, float> {
+    static constexpr int TX = 30, TY = 14, CHUNK = 48;
+};
+template <>
+struct Tile<D3Q19, double> {
+    static constexpr int TX = 30, TY = 6, CHUNK = 16;
+};
+template <>
+struct Tile<D2Q9, float> {
+    static constexpr int TX = 254, TY = 1, CHUNK = 32;
+};
+template <>
+struct Tile<D2Q9, double> {
+    static constexpr int TX = 254, TY = 1, CHUNK = 32;
+};
+
+}  // namespace
+
+template <class L, class S>
+hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, hipStream_t st) {
+    using TL = Tile<L, S>;
+    const GridP& g = a.grid;
+    FusedArgs fa;
+    fa.tiles_x = (g.nx + TL::TX - 1) / TL::TX;
+    fa.tiles_y = L::D == 3 ? (g.ny + TL::TY - 1) / TL::TY : 1;
+    const int nm = L::D == 3 ? g.nz : g.ny;
+    fa.chunk = chunk > 0 ? chunk : TL::CHUNK;
+    fa.chunks = (nm + fa.chunk - 1) / fa.chunk;
+    fa.total = fa.tiles_x * fa.tiles_y * fa.chunks;
+    fa.per_xcd = (fa.total + 7) / 8;
+    fa.small = (g.nx < TL::TX + 4) || (L::D == 3 && g.ny < TL::TY + 4) || nm < 8;
+    const int grid = fa.per_xcd * 8;
+    constexpr int threads = (TL::TX + 2) * (L::D == 3 ? TL::TY + 2 : 1);
+    hipLaunchKernelGGL((k_fused<L, S, S, TL::TX, TL::TY>), dim3(grid), dim3(threads), 0, st, a, fa, A, B);
+    return hipGetLastError();
+}
+
+template hipError_t launch_fused_step<D2Q9, float>(const SweepArgs&, StateP<float>, StateP<float>, int, hipStream_t);
+template hipError_t launch_fused_step<D2Q9, double>(const SweepArgs&, StateP<double>, StateP<double>, int,
+                                                    hipStream_t);
+template hipError_t launch_fused_step<D3Q19, float>(const SweepArgs&, StateP<float>, StateP<float>, int,
+                                                    hipStream_t);
+template hipError_t launch_fused_step<D3Q19, double>(const SweepArgs&, StateP<double>, StateP<double>, int,
+                                                     hipStream_t);
+
+}  // namespace lbmib

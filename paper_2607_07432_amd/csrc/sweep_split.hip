@@ -154,10 +154,10 @@ __global__ void __launch_bounds__(TPB) k_collide(SweepArgs a, StateP<S> A, State
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) fcol[i * N + n] = fc[i];
     if (r >= 0) {
-        a.rows.h2off[r] = H2n[0][1];
+        a.rows.h2off_out[r] = H2n[0][1];
         if (D == 3) {
-            a.rows.h2off[(long long)nr + r] = H2n[0][2];
-            a.rows.h2off[2LL * nr + r] = H2n[1][2];
+            a.rows.h2off_out[(long long)nr + r] = H2n[0][2];
+            a.rows.h2off_out[2LL * nr + r] = H2n[1][2];
         }
     }
     // New diagonal history into B, with the closure of the x boundaries.
@@ -379,7 +379,7 @@ __global__ void k_import(SweepArgs a, StateP<S> A, int c, const double* in, int*
     const int r = a.rows.rowmap[n];
     const int k = (p == 0 && q == 1) ? 0 : (p == 0 ? 1 : 2);
     if (r >= 0)
-        a.rows.h2off[(long long)k * a.rows.nrows + r] = in[n];
+        a.rows.h2off_out[(long long)k * a.rows.nrows + r] = in[n];
     else if (in[n] != 0.0)
         atomicOr(bad, 1);
 }

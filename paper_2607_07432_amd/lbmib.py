@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, 'liblbmib.so')
 
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_STATE, LBM_E_NONFINITE = 0, -1, -2, -3, -4, -5
 F32, F64 = 32, 64
+SWEEP_FUSED, SWEEP_THREE_PASS = 0, 1
 BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
 
 EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step', 'lbm_step_timed',
@@ -33,7 +34,7 @@ class LbmError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [('dim', ctypes.c_int), ('nx', ctypes.c_int), ('ny', ctypes.c_int), ('nz', ctypes.c_int),
                 ('precision', ctypes.c_int), ('bc_x', ctypes.c_int), ('kernel', ctypes.c_int),
-                ('max_markers', ctypes.c_int), ('with_aC', ctypes.c_int), ('pad0', ctypes.c_int),
+                ('max_markers', ctypes.c_int), ('with_aC', ctypes.c_int), ('sweep', ctypes.c_int),
                 ('gamma', ctypes.c_double), ('mu', ctypes.c_double), ('lambda_', ctypes.c_double),
                 ('sigma', ctypes.c_double), ('rho_inf', ctypes.c_double), ('u_inf', ctypes.c_double * 3),
                 ('T_inf', ctypes.c_double), ('ref_len', ctypes.c_double), ('ref_area', ctypes.c_double),
@@ -100,7 +101,7 @@ def _llptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)) if a is not None else None
 
 
-def params_from_case(case, precision=F64, max_markers=None, with_aC=True):
+def params_from_case(case, precision=F64, max_markers=None, with_aC=True, sweep=0):
     p = Params()
     p.dim = case.dim
     p.nx, p.ny = case.dims[0], case.dims[1]
@@ -111,6 +112,7 @@ def params_from_case(case, precision=F64, max_markers=None, with_aC=True):
     m = len(case.X) if case.X is not None else 0
     p.max_markers = max_markers if max_markers is not None else max(m, 1)
     p.with_aC = 1 if with_aC else 0
+    p.sweep = sweep
     p.gamma, p.mu, p.lambda_, p.sigma = case.gamma, case.mu, case.lam, case.sigma
     p.rho_inf = case.rho_inf
     for a in range(3):
@@ -148,8 +150,9 @@ class Solver:
         self.m = 0
 
     @classmethod
-    def from_case(cls, case, precision=F64, max_markers=None, with_aC=True, device='cuda:0', markers=True):
-        s = cls(params_from_case(case, precision, max_markers, with_aC), device)
+    def from_case(cls, case, precision=F64, max_markers=None, with_aC=True, device='cuda:0', markers=True,
+                  sweep=0):
+        s = cls(params_from_case(case, precision, max_markers, with_aC, sweep), device)
         if markers and case.X is not None:
             s.set_markers(case.X, case.n, case.u_wall, case.t_kind, case.t_value, case.method)
         return s

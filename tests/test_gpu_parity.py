@@ -65,8 +65,11 @@ def report(case, new, f1, e1, H1):
           f'{np.unravel_index(np.argmax(np.abs(e1 - new.rhoE)), e1.shape)}; |dH2|={np.abs(H1 - new.H2).max():.2e}')
 
 
-def solver_for(lbmib, case, precision=64):
-    return lbmib.Solver.from_case(case, precision=precision)
+def solver_for(lbmib, case, precision=64, sweep=0):
+    return lbmib.Solver.from_case(case, precision=precision, sweep=sweep)
+
+
+SWEEPS = {'fused': 0, 'threepass': 1}
 
 
 @pytest.mark.parametrize('name', list(CASES))
@@ -91,13 +94,14 @@ def test_index_lists_bit_exact(lbmib, name):
     assert np.abs(h['xstar'] - g.Xstar).max() < 1e-12
 
 
+@pytest.mark.parametrize('sweep', list(SWEEPS))
 @pytest.mark.parametrize('name', list(CASES))
-def test_one_step_fp64_parity(lbmib, name):
+def test_one_step_fp64_parity(lbmib, name, sweep):
     case = CASES[name]()
     g = oracle_geometry(case)
     mk = oracle_markers(case)
     st = random_state(case, g, seed=11)
-    s = solver_for(lbmib, case)
+    s = solver_for(lbmib, case, sweep=SWEEPS[sweep])
     s.set_state(st.f, st.rhoE, st.H2)
     f0, e0, H0 = s.get_state()
     # populations are stored as f - w_i: the FP64 round trip is exact to an ulp of f
@@ -119,15 +123,16 @@ def test_one_step_fp64_parity(lbmib, name):
     assert rel(ms['TP'][act], mf['TP'][act]) < TOL64
 
 
+@pytest.mark.parametrize('sweep', list(SWEEPS))
 @pytest.mark.parametrize('name', ['cyl_R_io', 'sph_R_iso'])
-def test_multi_step_fp64_parity_and_loads(lbmib, name):
+def test_multi_step_fp64_parity_and_loads(lbmib, name, sweep):
     case = CASES[name]()
     lat = for_dim(case.dim)
     prm = oracle_params(case)
     g = oracle_geometry(case)
     mk = oracle_markers(case)
     st = olbm.freestream_state(lat, prm, tuple(case.dims[::-1]))
-    s = solver_for(lbmib, case)
+    s = solver_for(lbmib, case, sweep=SWEEPS[sweep])
     nsteps = 20
     for k in range(nsteps):
         old = st
@@ -161,14 +166,15 @@ def test_multi_step_fp64_parity_and_loads(lbmib, name):
     assert abs(s.residual() - r) <= 1e-10 * r
 
 
-def test_fp32_error_budget_config1(lbmib):
+@pytest.mark.parametrize('sweep', list(SWEEPS))
+def test_fp32_error_budget_config1(lbmib, sweep):
     case = wl.config1(steps=1)
     lat = for_dim(2)
     prm = oracle_params(case)
     g = oracle_geometry(case)
     mk = oracle_markers(case)
     st = olbm.freestream_state(lat, prm, (100, 200))
-    s = solver_for(lbmib, case, precision=32)
+    s = solver_for(lbmib, case, precision=32, sweep=SWEEPS[sweep])
     n = 100
     for _ in range(n):
         st, mf = oracle_step(case, st, g, mk)
