@@ -124,6 +124,7 @@ struct lbm_handle {
     std::vector<double> host_stage;
     int method = 0;
     int chunk = 0;         // planes per workgroup of the fused sweep (0: per-lattice default)
+    int variant = 0;       // tile variant of the fused sweep (tuning)
     int markers_set = 0;
     int stepped = 0;       // a step has run since the body was set
     int any_step = 0;
@@ -276,11 +277,12 @@ int lbm_init_grid(const lbm_params* p, void* ws, size_t bytes, void* stream, lbm
     h->N = (long long)p->nx * p->ny * p->nz;
     h->stream = (hipStream_t)stream;
     if (const char* ch = std::getenv("LBMIB_FUSED_CHUNK")) h->chunk = std::atoi(ch);
+    if (const char* tv = std::getenv("LBMIB_FUSED_TILE")) h->variant = std::atoi(tv);
     layout(*p, (char*)ws, &h->d);
 
     SweepArgs& a = h->args;
     a.grid = {p->nx, p->ny, p->nz, h->N, p->bc_x};
-    a.gas = {p->mu, p->lambda_, p->gamma, p->sigma, Cv, Cv + 1.0 / 3.0, p->with_aC};
+    a.gas = {p->mu, p->lambda_, p->gamma, p->sigma, Cv, Cv + 1.0 / 3.0, p->with_aC, 1.0 / Cv};
     for (int i = 0; i < 19; ++i) a.fs.fdev[i] = i < Q ? fd[i] : 0.0;
     double uu = 0;
     for (int b = 0; b < 3; ++b) uu += u[b] * u[b];
@@ -420,7 +422,7 @@ int run_steps(lbm_handle* h, int n, hipEvent_t* ev) {
                 if (h->p.sweep == LBM_SWEEP_THREE_PASS)
                     r = launch_split_step<LT, ST, ST>(h->args, A, B, M, fcol, h->stream);
                 else
-                    r = launch_fused_step<LT, ST>(h->args, A, B, h->chunk, h->stream);
+                    r = launch_fused_step<LT, ST>(h->args, A, B, h->chunk, h->variant, h->stream);
             }
             if (r == hipSuccess && e4) r = hipEventRecord(e4[3], h->stream);
             if (r == hipSuccess && last)

@@ -18,11 +18,13 @@ namespace lbmib {
 struct Gas {
     double mu, lambda_, gamma, sigma, Cv, Cp;
     int with_aC;
+    double inv_Cv;      // 1 / Cv
 };
 
 template <class L, class C>
 struct Node {
     C rho;          // density
+    C inv_rho;      // 1 / rho
     C u[3];         // velocity with the half-force correction, Eq. (9)
     C T;            // temperature of the predicted (force-free) state
 };
@@ -157,7 +159,7 @@ __device__ __forceinline__ void collide(const Gas& g, const C* fd, const Node<L,
                 if (L::c[i][a] * L::c[i][b] != 0) M2[a][b] += C(L::c[i][a] * L::c[i][b]) * fd[i];
 
     // Eq. (A.7): Pi = sigma [dev(M2) - dev(rho u u) + H2/2] - (1 - sigma) rho cs^2 taubar S.
-    const C taubar = C(g.mu) / (rho * C(CS2)) + C(0.5);   // tau = nu / cs^2, Eq. (6)
+    const C taubar = C(3.0 * g.mu) * n.inv_rho + C(0.5);   // tau = nu / cs^2, Eq. (6)
     const C om = C(1) - C(1) / taubar;
     C trP = 0;
 #pragma unroll
@@ -176,7 +178,7 @@ __device__ __forceinline__ void collide(const Gas& g, const C* fd, const Node<L,
             C pop = M2[a][b] - rho * u[a] * u[b] + C(0.5) * H2[a][b];
             C S = s.du[a][b] + s.du[b][a];
             if (a == b) {
-                pop -= trP / C(D);
+                pop -= trP * C(1.0 / D);
                 S -= C(2.0 / D) * div;
             }
             Pi[a][b] = sig * pop - fdc * S;
@@ -222,7 +224,7 @@ __device__ __forceinline__ void collide(const Gas& g, const C* fd, const Node<L,
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = 0; b < D; ++b) H2new[a][b] = aF[a][b] - (a == b ? tra / C(D) : C(0));
+        for (int b = 0; b < D; ++b) H2new[a][b] = aF[a][b] - (a == b ? tra * C(1.0 / D) : C(0));
 }
 
 // Velocities below U_ZERO count as zero in both sign decisions of the MUSCL operator
@@ -249,14 +251,14 @@ struct Cell {
 template <class C>
 __device__ __forceinline__ void muscl_weights(C ua, C ub, C* w) {
     if (C(0.5) * (ua + ub) >= C(-U_ZERO)) {
-        const C eta = (C(2) * ua - sgn(ua)) / C(3);
+        const C eta = (C(2) * ua - sgn(ua)) * C(1.0 / 3.0);
         const C s = (C(1) - ua) * C(0.25);
         w[0] = -s * (C(1) + eta);
         w[1] = C(1) + C(2) * s * eta;
         w[2] = s * (C(1) - eta);
         w[3] = 0;
     } else {
-        const C eta = (C(2) * ub - sgn(ub)) / C(3);
+        const C eta = (C(2) * ub - sgn(ub)) * C(1.0 / 3.0);
         const C s = (C(1) + ub) * C(0.25);
         w[0] = 0;
         w[1] = s * (C(1) + eta);

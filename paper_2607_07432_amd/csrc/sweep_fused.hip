@@ -143,16 +143,17 @@ __global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(S
                     if (L::c[i][b]) j[b] += C(L::c[i][b]) * f;
             }
             const C rho = C(1) + drho;
+            const C ir = C(1) / rho;
             C uu = 0;
 #pragma unroll
-            for (int b = 0; b < D; ++b) uu += (j[b] / rho) * (j[b] / rho);
-            const C T = ((C(pa_e[kk]) + C(a.fs.e_ref)) / rho - C(0.5) * uu) / C(a.gas.Cv);
+            for (int b = 0; b < D; ++b) uu += (j[b] * ir) * (j[b] * ir);
+            const C T = ((C(pa_e[kk]) + C(a.fs.e_ref)) * ir - C(0.5) * uu) * C(a.gas.inv_Cv);
             const int r = pa_r[kk];
             sm.mac[sl][0][k] = rho;
 #pragma unroll
             for (int b = 0; b < D; ++b) {
                 const C fib = r >= 0 ? C(a.rows.fib[(long long)b * a.rows.nrows + r]) : C(0);
-                sm.mac[sl][1 + b][k] = (j[b] + C(0.5) * fib) / rho;
+                sm.mac[sl][1 + b][k] = (j[b] + C(0.5) * fib) * ir;
             }
             sm.mac[sl][1 + D][k] = T;
         }
@@ -195,6 +196,7 @@ __global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(S
             const Cell<L, C> c0 = mcell(sl, k2);
             Node<L, C> nd;
             nd.rho = c0.rho;
+            nd.inv_rho = C(1) / c0.rho;
             nd.T = c0.T;
 #pragma unroll
             for (int b = 0; b < 3; ++b) nd.u[b] = c0.u[b];
@@ -462,31 +464,39 @@ struct Tile<D2Q9, double> {
 
 }  // namespace
 
-template <class L, class S>
-hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, hipStream_t st) {
-    using TL = Tile<L, S>;
+template <class L, class S, int TX, int TY>
+hipError_t launch_fused_tile(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, int default_chunk,
+                             hipStream_t st) {
     const GridP& g = a.grid;
     FusedArgs fa;
-    fa.tiles_x = (g.nx + TL::TX - 1) / TL::TX;
-    fa.tiles_y = L::D == 3 ? (g.ny + TL::TY - 1) / TL::TY : 1;
+    fa.tiles_x = (g.nx + TX - 1) / TX;
+    fa.tiles_y = L::D == 3 ? (g.ny + TY - 1) / TY : 1;
     const int nm = L::D == 3 ? g.nz : g.ny;
-    fa.chunk = chunk > 0 ? chunk : TL::CHUNK;
+    fa.chunk = chunk > 0 ? chunk : default_chunk;
     fa.chunks = (nm + fa.chunk - 1) / fa.chunk;
     fa.total = fa.tiles_x * fa.tiles_y * fa.chunks;
     fa.per_xcd = (fa.total + 7) / 8;
-    fa.small = (g.nx < TL::TX + 4) || (L::D == 3 && g.ny < TL::TY + 4) || nm < 8;
+    fa.small = (g.nx < TX + 4) || (L::D == 3 && g.ny < TY + 4) || nm < 8;
     const int grid = fa.per_xcd * 8;
-    constexpr int threads = (TL::TX + 2) * (L::D == 3 ? TL::TY + 2 : 1);
-    hipLaunchKernelGGL((k_fused<L, S, S, TL::TX, TL::TY>), dim3(grid), dim3(threads), 0, st, a, fa, A, B);
+    constexpr int threads = (TX + 2) * (L::D == 3 ? TY + 2 : 1);
+    hipLaunchKernelGGL((k_fused<L, S, S, TX, TY>), dim3(grid), dim3(threads), 0, st, a, fa, A, B);
     return hipGetLastError();
 }
 
-template hipError_t launch_fused_step<D2Q9, float>(const SweepArgs&, StateP<float>, StateP<float>, int, hipStream_t);
-template hipError_t launch_fused_step<D2Q9, double>(const SweepArgs&, StateP<double>, StateP<double>, int,
-                                                    hipStream_t);
-template hipError_t launch_fused_step<D3Q19, float>(const SweepArgs&, StateP<float>, StateP<float>, int,
-                                                    hipStream_t);
-template hipError_t launch_fused_step<D3Q19, double>(const SweepArgs&, StateP<double>, StateP<double>, int,
-                                                     hipStream_t);
+// variant 1 selects the 14 x 14 tile (256 threads, two workgroups per CU) for FP32 D3Q19.
+template <class L, class S>
+hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, int variant,
+                             hipStream_t st) {
+    using TL = Tile<L, S>;
+    if constexpr (L::D == 3 && sizeof(S) == 4) {
+        if (variant == 1) return launch_fused_tile<L, S, 14, 14>(a, A, B, chunk, 32, st);
+    }
+    return launch_fused_tile<L, S, TL::TX, TL::TY>(a, A, B, chunk, TL::CHUNK, st);
+}
+
+template hipError_t launch_fused_step<D2Q9, float>(const SweepArgs&, StateP<float>, StateP<float>, int, int, hipStream_t);
+template hipError_t launch_fused_step<D2Q9, double>(const SweepArgs&, StateP<double>, StateP<double>, int, int, hipStream_t);
+template hipError_t launch_fused_step<D3Q19, float>(const SweepArgs&, StateP<float>, StateP<float>, int, int, hipStream_t);
+template hipError_t launch_fused_step<D3Q19, double>(const SweepArgs&, StateP<double>, StateP<double>, int, int, hipStream_t);
 
 }  // namespace lbmib

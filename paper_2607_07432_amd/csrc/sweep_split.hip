@@ -99,6 +99,7 @@ __global__ void __launch_bounds__(TPB) k_collide(SweepArgs a, StateP<S> A, State
     const Cell<L, C> c0 = cell_at<L, C>(M, N, n);
     Node<L, C> nd;
     nd.rho = c0.rho;
+    nd.inv_rho = C(1) / c0.rho;
     nd.T = c0.T;
 #pragma unroll
     for (int b = 0; b < 3; ++b) nd.u[b] = c0.u[b];
