@@ -22,6 +22,8 @@ import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -77,7 +79,6 @@ def copy_kernel(nbytes):
 
 def cpu_baseline(seconds_hint=20.0):
     """FP64 oracle on a bounded crop: the same sphere (D = 32, 3217 markers) in 96 x 48 x 48."""
-    import numpy as np  # noqa: F401
     from oracle import ib as oib
     from oracle import lbm as olbm
     from oracle.lattice import for_dim
@@ -105,6 +106,62 @@ def cpu_baseline(seconds_hint=20.0):
                       f'({platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()})'}
 
 
+def bench_batch(args):
+    """64 uneven 2D ellipse cases (256x128 .. 1024x512, FP32) in one batch: graph-replayed steps."""
+    import torch
+    from paper_2607_07432_amd import lbmib
+    from paper_2607_07432_amd import workloads as wl
+    cases = wl.batched_cases(64)
+    prec = lbmib.F64 if args.precision == 64 else lbmib.F32
+    sols = [lbmib.Solver.from_case(c, precision=prec) for c in cases]
+    N = sum(c.n_nodes for c in cases)
+    M = sum(len(c.X) for c in cases)
+    t0 = time.perf_counter()
+    batch = lbmib.Batch(sols, autotune=True)
+    cfg = batch.config()
+    print(f'[bench] batch of {len(cases)} cases, N={N}, markers={M}, tuned {cfg} in '
+          f'{time.perf_counter() - t0:.1f} s', file=sys.stderr, flush=True)
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    glups = N * args.steps / (t1 - t0) / 1e9
+    kernel_ms = batch.step_timed(min(args.steps, 50))
+    res = batch.residuals()
+    bad = [k for k, r in enumerate(res) if not np.isfinite(r)]
+    n_bad = len(bad)
+    for k in bad:
+        c = cases[k]
+        print(f'[bench] case {k} non-finite: {c.dims} Ma {c.extra["mach"]:.3f} Re {c.extra["reynolds"]:.1f} '
+              f'tau {3 * c.mu + 0.5:.4f} kappa {wl.conduction_number(c):.3f}', file=sys.stderr, flush=True)
+    print(f'[bench] {ms_per_step:.3f} ms/step, {glups:.2f} GLUPS (graph replay), kernels (markers, spread, '
+          f'sweep) ms {kernel_ms.round(4).tolist()}, residual max {np.nanmax(res):.3e}', file=sys.stderr, flush=True)
+    vals = state_values_per_node(2, 9)
+    bytes_per_node = 2 * vals * (args.precision // 8)
+    sweep_ms = float(kernel_ms[2])
+    achieved = bytes_per_node * N / (sweep_ms * 1e-3) / 1e9
+    out = {
+        'metric': 'GLUPS of fused LBM+FODIBM step (batched 2D cases)',
+        'value': round(glups, 4), 'unit': 'GLUPS', 'n_gpus': 1, 'steps': args.steps, 'warmup': args.warmup,
+        'ms_per_step': round(ms_per_step, 5), 'higher_is_better': True, 'scaling': 'weak', 'vs_baseline': None,
+        'dtype': f'f{args.precision}', 'data': 'synthetic',
+        'config': {'workload': 'batch64: 64 uneven D2Q9 ellipse cases 256x128..1024x512, 64..256 markers, '
+                               'FODIBM-R adiabatic no-slip, Ma 0.1-0.5, Re 20-200, one persistent graph-replayed step',
+                   'nodes': N, 'markers': M, 'tuned': cfg, 'parallelism': 'single GPU'},
+        'roofline': {'bound': 'hbm', 'kernel': 'persistent batched fused sweep', 'achieved': round(achieved, 1),
+                     'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4),
+                     'bytes_per_node': bytes_per_node, 'sweep_ms': round(sweep_ms, 5), 'traffic': None},
+        'kernel_ms': {'markers': round(float(kernel_ms[0]), 5), 'spread': round(float(kernel_ms[1]), 5),
+                      'sweep': round(sweep_ms, 5)},
+        'nonfinite_cases': n_bad,
+    }
+    batch.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -115,6 +172,7 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--copy-kernel', type=int, default=0)
     ap.add_argument('--sweep', choices=('fused', 'threepass'), default='fused')
+    ap.add_argument('--workload', choices=('sphere3d', 'batch64'), default='sphere3d')
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -123,6 +181,9 @@ def main():
         sys.exit(2)
     if args.copy_kernel:
         copy_kernel(args.copy_kernel)
+        return
+    if args.workload == 'batch64':
+        bench_batch(args)
         return
 
     import torch

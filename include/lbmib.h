@@ -162,6 +162,52 @@ int ib_geometry(lbm_handle* h, long long* supp_ptr, long long* supp_node, double
 int ib_marker_state(lbm_handle* h, double* F, double* Wib, double* Qib, double* rho, double* T,
                     double* uP, double* TP);
 
+/* ---- Batches of independent 2D grids -------------------------------------------------------
+ * Many D2Q9 cases of uneven size (each its own handle, body and parameters) advanced together:
+ * per step one launch computes the marker forces of every case, one spreads them, and one
+ * persistent launch runs the fused sweep (the same per-node update as lbm_step, Sec. 2.5 and
+ * Appendix A) over a queue of tiles of all cases; the steps are replayed from captured HIP graphs.
+ * The handles keep their own state: lbm_fields, ib_wall_loads, lbm_residual etc. work on each
+ * case after batch steps exactly as after lbm_step. Results per case are identical to lbm_step
+ * except the residual, which is reduced in a different (fixed) order.
+ * Requirements: every case is 2D, all share the precision and the HIP stream; a handle appears
+ * once; the handles and the workspace outlive the batch. A case may be changed between batch
+ * calls (ib_set_markers, lbm_step, lbm_set_fields, lbm_set_state); the batch notices and
+ * rebuilds its tables. Not thread-safe. */
+typedef struct lbm_batch lbm_batch;
+
+/* Device workspace bytes for a batch of these n cases (0 if invalid). */
+size_t lbm_batch_workspace_bytes(lbm_handle* const* cases, int n);
+
+/* Create a batch. dev_workspace: caller-owned device memory of at least
+ * lbm_batch_workspace_bytes bytes, 256-byte aligned. autotune = 1 times the sweep for each tile
+ * width (62, 126, 254 nodes) and chunk length (16, 32, 64, 128 rows) on the current states and
+ * keeps the fastest (the states are left unchanged); 0 takes 62 x 32.
+ * Errors: LBM_E_INVAL (see requirements), LBM_E_NOMEM, LBM_E_HIP. */
+int lbm_batch_create(lbm_handle* const* cases, int n, void* dev_workspace, size_t bytes, int autotune,
+                     lbm_batch** out);
+
+/* Enqueue n steps of every case (graph replays) on the shared stream; the last step also
+ * computes each case's residual (lbm_residual). Asynchronous. Errors: LBM_E_INVAL, LBM_E_HIP. */
+int lbm_batch_step(lbm_batch* b, int n);
+
+/* As lbm_batch_step but launched without graphs and timed with HIP events: kernel_ms[0] marker
+ * forces, [1] spreading, [2] sweep, each the average per step over all cases. Synchronises. */
+int lbm_batch_step_timed(lbm_batch* b, int n, double* kernel_ms);
+
+/* Use tile width tile_x (62, 126 or 254 nodes) and chunks of `chunk` rows (>= 1) for the sweep.
+ * Errors: LBM_E_INVAL (other values), LBM_E_HIP. */
+int lbm_batch_set_tile(lbm_batch* b, int tile_x, int chunk);
+
+/* cfg[6] = {tile width, chunk rows, persistent grid size, sweep work items, markers, CSR rows}. */
+int lbm_batch_config(lbm_batch* b, int* cfg);
+
+/* Release the batch (not the handles or the workspace). */
+void lbm_batch_destroy(lbm_batch* b);
+
+/* Message of the last error of this batch (of the last failed lbm_batch_create if b is NULL). */
+const char* lbm_batch_last_error(lbm_batch* b);
+
 /* Release the handle (not the caller's workspace). */
 void lbm_destroy(lbm_handle* h);
 

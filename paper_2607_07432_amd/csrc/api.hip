@@ -11,9 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lbmib.h"
-#include "kernels.hpp"
-#include "precompute.hpp"
+#include "handle.hpp"
 
 using namespace lbmib;
 
@@ -35,23 +33,6 @@ struct Layout {
         off += count * sizeof(T);
         return p;
     }
-};
-
-struct Dev {
-    // state (storage precision), ping-pong
-    void *fA, *eA, *hA, *fB, *eB, *hB;
-    void* work;     // M [(D+2) N] followed by fcol [Q N], compute precision
-    int* rowmap;
-    double* partials;
-    double* resid;  // [2]
-    double* loads;  // [16]
-    int* flag;
-    // markers
-    long long *supp_ptr, *supp_node, *proj_ptr, *proj_node, *tw_ptr, *tw_node;
-    double *supp_w, *proj_w, *tw_w, *phi, *dbv, *W, *u_wall, *t_value, *G, *diag, *eps;
-    int* t_kind;
-    long long *rows, *row_ptr, *col_marker;
-    double *col_s, *fib, *fE, *h2off, *h2off2;   // sparse history, ping-pong with the state
 };
 
 int lattice_q(int dim) { return dim == 2 ? 9 : 19; }
@@ -111,26 +92,6 @@ bool is_fin(double v) { return std::isfinite(v); }
 
 }  // namespace
 
-struct lbm_handle {
-    lbm_params p;
-    int D = 0, Q = 0;
-    long long N = 0;
-    hipStream_t stream = nullptr;
-    Dev d{};
-    int cur = 0;           // 0: state A is current, 1: state B
-    SweepArgs args{};
-    MarkersP mk{};
-    Geometry geom;
-    std::vector<double> host_stage;
-    int method = 0;
-    int chunk = 0;         // planes per workgroup of the fused sweep (0: per-lattice default)
-    int variant = 0;       // tile variant of the fused sweep (tuning)
-    int markers_set = 0;
-    int stepped = 0;       // a step has run since the body was set
-    int any_step = 0;
-    std::string err;
-};
-
 namespace {
 
 int fail(lbm_handle* h, int code, const std::string& msg) {
@@ -147,14 +108,6 @@ int fail(lbm_handle* h, int code, const std::string& msg) {
         if (e_ != hipSuccess) return fail((h), LBM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-template <class S>
-StateP<S> stateA(lbm_handle* h) {
-    return {(S*)h->d.fA, (S*)h->d.eA, (S*)h->d.hA};
-}
-template <class S>
-StateP<S> stateB(lbm_handle* h) {
-    return {(S*)h->d.fB, (S*)h->d.eB, (S*)h->d.hB};
-}
 template <class S>
 StateP<S> current(lbm_handle* h) {
     return h->cur == 0 ? stateA<S>(h) : stateB<S>(h);
@@ -209,6 +162,12 @@ void refresh_args(lbm_handle* h) {
     m.diag = h->d.diag;
     m.eps = h->d.eps;
 }
+
+}  // namespace
+
+void lbmib::refresh_handle_args(lbm_handle* h) { refresh_args(h); }
+
+namespace {
 
 int validate_params(const lbm_params* p, std::string& why) {
     if (!p) return why = "params is NULL", LBM_E_INVAL;
@@ -392,6 +351,7 @@ int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal, 
     HIPCHK(h, hipStreamSynchronize(st));   // host vectors above must outlive the copies
     h->markers_set = m > 0;
     h->stepped = 0;
+    h->geom_version++;
     return LBM_OK;
 }
 

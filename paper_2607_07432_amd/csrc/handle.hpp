@@ -1,0 +1,70 @@
+// Host-side handle of one grid, shared by the single-grid API and the batch API.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lbmib.h"
+#include "kernels.hpp"
+#include "precompute.hpp"
+
+namespace lbmib {
+
+// Device arrays carved out of the caller's workspace.
+struct Dev {
+    // state (storage precision), ping-pong
+    void *fA, *eA, *hA, *fB, *eB, *hB;
+    void* work;     // M [(D+2) N] followed by fcol [Q N], compute precision
+    int* rowmap;
+    double* partials;
+    double* resid;  // [2]
+    double* loads;  // [16]
+    int* flag;
+    // markers
+    long long *supp_ptr, *supp_node, *proj_ptr, *proj_node, *tw_ptr, *tw_node;
+    double *supp_w, *proj_w, *tw_w, *phi, *dbv, *W, *u_wall, *t_value, *G, *diag, *eps;
+    int* t_kind;
+    long long *rows, *row_ptr, *col_marker;
+    double *col_s, *fib, *fE, *h2off, *h2off2;   // sparse history, ping-pong with the state
+};
+
+}  // namespace lbmib
+
+struct lbm_handle {
+    lbm_params p;
+    int D = 0, Q = 0;
+    long long N = 0;
+    hipStream_t stream = nullptr;
+    lbmib::Dev d{};
+    int cur = 0;           // 0: state A is current, 1: state B
+    lbmib::SweepArgs args{};
+    lbmib::MarkersP mk{};
+    lbmib::Geometry geom;
+    std::vector<double> host_stage;
+    int method = 0;
+    int chunk = 0;         // planes per workgroup of the fused sweep (0: per-lattice default)
+    int variant = 0;       // tile variant of the fused sweep (tuning)
+    int markers_set = 0;
+    int stepped = 0;       // a step has run since the body was set
+    int any_step = 0;
+    int geom_version = 0;  // incremented by every ib_set_markers
+    std::string err;
+};
+
+namespace lbmib {
+
+template <class S>
+StateP<S> stateA(lbm_handle* h) {
+    return {(S*)h->d.fA, (S*)h->d.eA, (S*)h->d.hA};
+}
+template <class S>
+StateP<S> stateB(lbm_handle* h) {
+    return {(S*)h->d.fB, (S*)h->d.eB, (S*)h->d.hB};
+}
+
+// Recompute the kernel argument blocks of a handle from its current state index and body.
+void refresh_handle_args(lbm_handle* h);
+
+}  // namespace lbmib

@@ -46,10 +46,8 @@ __device__ __forceinline__ void predicted(const SweepArgs& a, StateP<S> A, long 
 // One wavefront per marker: Eqs. (14)/(12) interpolation, Eqs. (27)/(29) reconstruction,
 // Eqs. (20)-(22)/(30)-(32) forces.
 template <class L, class S>
-__global__ void __launch_bounds__(WAVE) k_markers(SweepArgs a, MarkersP mk, StateP<S> A) {
+__device__ __forceinline__ void marker_forces(const SweepArgs& a, const MarkersP& mk, StateP<S> A, int l, int lane) {
     constexpr int D = L::D;
-    const int l = blockIdx.x;
-    const int lane = threadIdx.x;
     const double phi = mk.phi[l];
     double* G = mk.G + (long long)l * (D + 2);
     double* dg = mk.diag + (long long)l * 8;
@@ -136,10 +134,27 @@ __global__ void __launch_bounds__(WAVE) k_markers(SweepArgs a, MarkersP mk, Stat
     dg[7] = 0.0;
 }
 
-// Eq. (15): g_i = sum_k s_ik G_k over the CSR row of node i (one lane per forced node).
-__global__ void __launch_bounds__(256) k_spread(int dim, MarkersP mk, RowsP rows) {
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= rows.nrows) return;
+template <class L, class S>
+__global__ void __launch_bounds__(WAVE) k_markers(SweepArgs a, MarkersP mk, StateP<S> A) {
+    marker_forces<L, S>(a, mk, A, blockIdx.x, threadIdx.x);
+}
+
+// Batch: one wavefront per marker of any case; the case is found from the marker numbering.
+template <class L, class S>
+__global__ void __launch_bounds__(WAVE) k_markers_batch(const CaseDesc<S>* __restrict__ cases, int ncases, int g) {
+    const int l = blockIdx.x;
+    int lo = 0, hi = ncases - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (cases[mid].marker0 <= l) lo = mid; else hi = mid - 1;
+    }
+    const CaseDesc<S>& cd = cases[lo];
+    const int cur = (cd.cur0 + g) & 1;
+    marker_forces<L, S>(cd.a[cur], cd.mk, cd.st[cur], l - cd.marker0, threadIdx.x);
+}
+
+// Eq. (15): g_i = sum_k s_ik G_k over the CSR row r of node i.
+__device__ __forceinline__ void spread_row(int dim, const MarkersP& mk, const RowsP& rows, int r) {
     double f[3] = {0, 0, 0}, e = 0;
     for (long long k = mk.row_ptr[r]; k < mk.row_ptr[r + 1]; ++k) {
         const double s = mk.col_s[k];
@@ -149,6 +164,27 @@ __global__ void __launch_bounds__(256) k_spread(int dim, MarkersP mk, RowsP rows
     }
     for (int b = 0; b < dim; ++b) rows.fib[(long long)b * rows.nrows + r] = f[b];
     rows.fE[r] = e;
+}
+
+// One lane per forced node.
+__global__ void __launch_bounds__(256) k_spread(int dim, MarkersP mk, RowsP rows) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= rows.nrows) return;
+    spread_row(dim, mk, rows, r);
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) k_spread_batch(const CaseDesc<S>* __restrict__ cases, int ncases, int total,
+                                                      int dim) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= total) return;
+    int lo = 0, hi = ncases - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (cases[mid].row0 <= r) lo = mid; else hi = mid - 1;
+    }
+    const CaseDesc<S>& cd = cases[lo];
+    spread_row(dim, cd.mk, cd.a[0].rows, r - cd.row0);
 }
 
 // Boundary errors of Eqs. (35), (36), (38) at each marker from the current fields.
@@ -272,6 +308,26 @@ hipError_t launch_loads(int dim, const MarkersP& mk, double* out, hipStream_t st
     hipLaunchKernelGGL(k_loads, dim3(1), dim3(256), 0, st, dim, mk, out);
     return hipGetLastError();
 }
+
+template <class L, class S>
+hipError_t launch_markers_batch(const CaseDesc<S>* cases, int ncases, int total_markers, int g, hipStream_t st) {
+    if (total_markers <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_markers_batch<L, S>), dim3(total_markers), dim3(WAVE), 0, st, cases, ncases, g);
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_spread_batch(const CaseDesc<S>* cases, int ncases, int total_rows, int dim, hipStream_t st) {
+    if (total_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_spread_batch<S>), dim3((total_rows + 255) / 256), dim3(256), 0, st, cases, ncases,
+                       total_rows, dim);
+    return hipGetLastError();
+}
+
+template hipError_t launch_markers_batch<D2Q9, float>(const CaseDesc<float>*, int, int, int, hipStream_t);
+template hipError_t launch_markers_batch<D2Q9, double>(const CaseDesc<double>*, int, int, int, hipStream_t);
+template hipError_t launch_spread_batch<float>(const CaseDesc<float>*, int, int, int, hipStream_t);
+template hipError_t launch_spread_batch<double>(const CaseDesc<double>*, int, int, int, hipStream_t);
 
 #define LBMIB_INST_IB(L, S)                                                                                    \
     template hipError_t launch_markers<L, S>(const SweepArgs&, const MarkersP&, StateP<S>, hipStream_t);       \

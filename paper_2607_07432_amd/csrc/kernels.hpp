@@ -65,6 +65,23 @@ struct MarkersP {
     double* eps;            // [m][4]: eps_dir, eps_neu, eps_iso, kind mask
 };
 
+// One case of a batch of independent 2D grids (an entry of a device table). Index k of a[] and
+// st[] belongs to the step parity at which state k is the current one; at batch step parity g
+// the current state is (cur0 + g) & 1.
+template <class S>
+struct CaseDesc {
+    SweepArgs a[2];         // a[k].rows.h2off / h2off_out: the history buffers when state k is current
+    StateP<S> st[2];        // state A, state B of the case
+    MarkersP mk;
+    int cur0;               // current state at batch parity 0
+    int tiles_x, chunk, small;
+    int item0;              // first sweep work item of the case (items: tiles_x per chunk of rows)
+    int marker0, row0;      // first marker and first CSR row of the case in the batch numbering
+    int part0, nparts, part_len;   // residual partial sums: first, count, nodes per partial
+    double resid_scale;     // 1 / (|u_inf| sqrt(N))
+    double* resid;          // [2] residual and non-finite flag of the case
+};
+
 // Split sweep (macros -> collide -> stream + fluxes + energy).
 template <class L, class S, class C>
 hipError_t launch_split_step(const SweepArgs& a, StateP<S> A, StateP<S> B, C* M, C* fcol, hipStream_t st);
@@ -98,5 +115,19 @@ hipError_t launch_loads(int dim, const MarkersP& mk, double* out, hipStream_t st
 hipError_t launch_rowmap(const long long* rows, int nrows, int* rowmap, hipStream_t st);
 
 int residual_parts(long long N);
+
+// Batch of 2D grids. Sweep tile widths: 62, 126 or 254 nodes (64, 128, 256 threads).
+template <class L, class S>
+hipError_t launch_fused_batch(const CaseDesc<S>* cases, int ncases, int total_items, int tx, int grid, int g,
+                              hipStream_t st);
+template <class L, class S>
+int fused_batch_occupancy(int tx);   // resident workgroups per CU, 0 if tx is not a batch tile width
+template <class L, class S>
+hipError_t launch_markers_batch(const CaseDesc<S>* cases, int ncases, int total_markers, int g, hipStream_t st);
+template <class S>
+hipError_t launch_spread_batch(const CaseDesc<S>* cases, int ncases, int total_rows, int dim, hipStream_t st);
+template <class L, class S>
+hipError_t launch_residual_batch(const CaseDesc<S>* cases, int ncases, int total_parts, double* partials, int g,
+                                 hipStream_t st);
 
 }  // namespace lbmib

@@ -76,29 +76,18 @@ struct FusedArgs {
 
 }  // namespace
 
+// One work item: the tile at (x0, y0) of planes [z0, z1) of one grid. small: a grid dimension
+// is smaller than a tile plus its halo (periodic indices by the general modulo).
 template <class L, class S, class C, int TX, int TY>
-__global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(SweepArgs a, FusedArgs fa, StateP<S> A, StateP<S> B) {
+__device__ __forceinline__ void fused_tile(const SweepArgs& a, StateP<S> A, StateP<S> B, int x0, int y0, int z0,
+                                           int z1, bool small, FusedSmem<L, S, C, TX, TY>& sm) {
     using G = FG<L, TX, TY>;
     constexpr int D = L::D;
-    __shared__ FusedSmem<L, S, C, TX, TY> sm;
-
     const GridP& g = a.grid;
     const long long N = g.N;
     const int nm = D == 3 ? g.nz : g.ny;               // length of the marching axis
-    // XCD-aware placement: consecutive logical workgroups (neighbouring tiles) share an XCD.
-    const int w = blockIdx.x;
-    const int logical = (w % 8) * fa.per_xcd + w / 8;
-    if (logical >= fa.total) return;
-    const int per_plane = fa.tiles_x * fa.tiles_y;
-    const int chunk = logical / per_plane;
-    const int rem = logical % per_plane;
-    const int x0 = (rem % fa.tiles_x) * TX;
-    const int y0 = D == 3 ? (rem / fa.tiles_x) * TY : 0;
-    const int z0 = chunk * fa.chunk;
-    const int z1 = min(z0 + fa.chunk, nm);
     const int t = threadIdx.x;
 
-    const bool small = fa.small != 0;
     auto wr = [&](int v, int n) { return small ? wrapm(v, n) : wrap1(v, n); };
     auto gnode = [&](int x, int y, int m) -> long long {
         const int xw = wr(x, g.nx);
@@ -441,6 +430,55 @@ __global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(S
     }
 }
 
+template <class L, class S, class C, int TX, int TY>
+__global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(SweepArgs a, FusedArgs fa, StateP<S> A, StateP<S> B) {
+    __shared__ FusedSmem<L, S, C, TX, TY> sm;
+    constexpr int D = L::D;
+    // XCD-aware placement: consecutive logical workgroups (neighbouring tiles) share an XCD.
+    const int w = blockIdx.x;
+    const int logical = (w % 8) * fa.per_xcd + w / 8;
+    if (logical >= fa.total) return;
+    const int per_plane = fa.tiles_x * fa.tiles_y;
+    const int chunk = logical / per_plane;
+    const int rem = logical % per_plane;
+    const int x0 = (rem % fa.tiles_x) * TX;
+    const int y0 = D == 3 ? (rem / fa.tiles_x) * TY : 0;
+    const int nm = D == 3 ? a.grid.nz : a.grid.ny;
+    const int z0 = chunk * fa.chunk;
+    const int z1 = min(z0 + fa.chunk, nm);
+    fused_tile<L, S, C, TX, TY>(a, A, B, x0, y0, z0, z1, fa.small != 0, sm);
+}
+
+// Persistent sweep over the work items of a batch of 2D grids. The items of one case are
+// consecutive (rows of tiles, then chunks along y); each XCD takes a contiguous range of the
+// item list and its workgroups stride through it, so that neighbouring tiles share an L2.
+template <class L, class S, int TX>
+__global__ void __launch_bounds__(TX + 2) k_fused_batch(const CaseDesc<S>* __restrict__ cases, int ncases, int total,
+                                                        int g) {
+    static_assert(L::D == 2, "batches hold 2D grids");
+    __shared__ FusedSmem<L, S, S, TX, 1> sm;
+    const int per_xcd = (total + 7) / 8;
+    const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8, nslots = gridDim.x / 8;
+    for (int k = slot; k < per_xcd; k += nslots) {
+        const int w = xcd * per_xcd + k;
+        if (w >= total) break;
+        int lo = 0, hi = ncases - 1;                  // last case with item0 <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (cases[mid].item0 <= w) lo = mid; else hi = mid - 1;
+        }
+        const CaseDesc<S>& cd = cases[lo];
+        const int cur = (cd.cur0 + g) & 1;
+        const int local = w - cd.item0;
+        const int chunk = local / cd.tiles_x;
+        const int x0 = (local % cd.tiles_x) * TX;
+        const int z0 = chunk * cd.chunk;
+        const int z1 = min(z0 + cd.chunk, cd.a[0].grid.ny);
+        __syncthreads();                              // the previous item's LDS reads are done
+        fused_tile<L, S, S, TX, 1>(cd.a[cur], cd.st[cur], cd.st[cur ^ 1], x0, 0, z0, z1, cd.small != 0, sm);
+    }
+}
+
 namespace {
 
 template <class L, class S>
@@ -493,6 +531,42 @@ hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int c
     }
     return launch_fused_tile<L, S, TL::TX, TL::TY>(a, A, B, chunk, TL::CHUNK, st);
 }
+
+template <class L, class S>
+hipError_t launch_fused_batch(const CaseDesc<S>* cases, int ncases, int total_items, int tx, int grid, int g,
+                              hipStream_t st) {
+    if (total_items <= 0) return hipSuccess;
+    if (grid < 8 || grid % 8) return hipErrorInvalidValue;
+    switch (tx) {
+        case 62:
+            hipLaunchKernelGGL((k_fused_batch<L, S, 62>), dim3(grid), dim3(64), 0, st, cases, ncases, total_items, g);
+            break;
+        case 126:
+            hipLaunchKernelGGL((k_fused_batch<L, S, 126>), dim3(grid), dim3(128), 0, st, cases, ncases, total_items, g);
+            break;
+        case 254:
+            hipLaunchKernelGGL((k_fused_batch<L, S, 254>), dim3(grid), dim3(256), 0, st, cases, ncases, total_items, g);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <class L, class S>
+int fused_batch_occupancy(int tx) {
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (tx == 62) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused_batch<L, S, 62>, 64, 0);
+    if (tx == 126) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused_batch<L, S, 126>, 128, 0);
+    if (tx == 254) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused_batch<L, S, 254>, 256, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+template hipError_t launch_fused_batch<D2Q9, float>(const CaseDesc<float>*, int, int, int, int, int, hipStream_t);
+template hipError_t launch_fused_batch<D2Q9, double>(const CaseDesc<double>*, int, int, int, int, int, hipStream_t);
+template int fused_batch_occupancy<D2Q9, float>(int);
+template int fused_batch_occupancy<D2Q9, double>(int);
 
 template hipError_t launch_fused_step<D2Q9, float>(const SweepArgs&, StateP<float>, StateP<float>, int, int, hipStream_t);
 template hipError_t launch_fused_step<D2Q9, double>(const SweepArgs&, StateP<double>, StateP<double>, int, int, hipStream_t);

@@ -22,7 +22,9 @@ BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
 EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step', 'lbm_step_timed',
            'ib_wall_loads', 'lbm_fields',
            'lbm_set_fields', 'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts',
-           'ib_geometry', 'ib_marker_state', 'lbm_destroy', 'lbm_last_error']
+           'ib_geometry', 'ib_marker_state', 'lbm_destroy', 'lbm_last_error',
+           'lbm_batch_workspace_bytes', 'lbm_batch_create', 'lbm_batch_step', 'lbm_batch_step_timed',
+           'lbm_batch_set_tile', 'lbm_batch_config', 'lbm_batch_destroy', 'lbm_batch_last_error']
 
 
 class LbmError(RuntimeError):
@@ -81,9 +83,21 @@ def load_library(path=LIB_PATH):
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.argtypes = [vp]
     lib.lbm_last_error.restype = ctypes.c_char_p
+    lib.lbm_batch_workspace_bytes.argtypes = [P(vp), i]
+    lib.lbm_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.lbm_batch_create.argtypes = [P(vp), i, vp, ctypes.c_size_t, i, P(vp)]
+    lib.lbm_batch_step.argtypes = [vp, i]
+    lib.lbm_batch_step_timed.argtypes = [vp, i, dp]
+    lib.lbm_batch_config.argtypes = [vp, ip]
+    lib.lbm_batch_set_tile.argtypes = [vp, i, i]
+    lib.lbm_batch_destroy.argtypes = [vp]
+    lib.lbm_batch_destroy.restype = None
+    lib.lbm_batch_last_error.argtypes = [vp]
+    lib.lbm_batch_last_error.restype = ctypes.c_char_p
     for name in ('lbm_init_grid', 'ib_set_markers', 'lbm_step', 'lbm_step_timed', 'ib_wall_loads', 'lbm_fields', 'lbm_set_fields',
                  'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts', 'ib_geometry',
-                 'ib_marker_state'):
+                 'ib_marker_state', 'lbm_batch_create', 'lbm_batch_step', 'lbm_batch_step_timed',
+                 'lbm_batch_config', 'lbm_batch_set_tile'):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -273,3 +287,76 @@ class Solver:
         self._check(self.lib.ib_marker_state(self.h, _dptr(F), _dptr(Wib), _dptr(Qib), _dptr(rho), _dptr(T),
                                              _dptr(uP), _dptr(TP)))
         return dict(F=F.reshape(m, D), Wib=Wib, Qib=Qib, rho=rho, T=T, uP=uP.reshape(m, D), TP=TP)
+
+
+class Batch:
+    """Independent 2D grids (Solver objects on one stream) advanced together by the batch API."""
+
+    def __init__(self, solvers, autotune=True):
+        import torch
+        if not solvers:
+            raise ValueError('empty batch')
+        self.lib = load_library()
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        arr = (ctypes.c_void_p * n)(*[s.h.value for s in self.solvers])
+        self._arr = arr
+        nbytes = self.lib.lbm_batch_workspace_bytes(arr, n)
+        if nbytes == 0:
+            raise LbmError(LBM_E_INVAL, 'invalid batch (2D cases of one precision on one stream)')
+        dev = self.solvers[0].device
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        ptr = (self.workspace.data_ptr() + 255) & ~255
+        b = ctypes.c_void_p()
+        rc = self.lib.lbm_batch_create(arr, n, ctypes.c_void_p(ptr), nbytes, 1 if autotune else 0, ctypes.byref(b))
+        if rc != LBM_OK:
+            raise LbmError(rc, self.lib.lbm_batch_last_error(None).decode())
+        self.b = b
+        self.nodes = sum(s.N for s in self.solvers)
+
+    def _check(self, rc):
+        if rc != LBM_OK:
+            raise LbmError(rc, self.lib.lbm_batch_last_error(self.b).decode())
+        return rc
+
+    def step(self, n=1):
+        self._check(self.lib.lbm_batch_step(self.b, int(n)))
+
+    def step_timed(self, n):
+        """n steps without graphs; returns the average per-step ms of (markers, spread, sweep)."""
+        ms = np.zeros(3)
+        self._check(self.lib.lbm_batch_step_timed(self.b, int(n), _dptr(ms)))
+        return ms
+
+    def set_tile(self, tile_x, chunk):
+        self._check(self.lib.lbm_batch_set_tile(self.b, int(tile_x), int(chunk)))
+
+    def config(self):
+        c = np.zeros(6, dtype=np.int32)
+        self._check(self.lib.lbm_batch_config(self.b, _iptr(c)))
+        return dict(tile_x=int(c[0]), chunk=int(c[1]), grid=int(c[2]), items=int(c[3]), markers=int(c[4]),
+                    rows=int(c[5]))
+
+    def residuals(self):
+        """Residual of every case after the last batch step (nan for a case whose state holds a
+        non-finite value)."""
+        out = []
+        for s in self.solvers:
+            try:
+                out.append(s.residual())
+            except LbmError as e:
+                if e.code != LBM_E_NONFINITE:
+                    raise
+                out.append(float('nan'))
+        return out
+
+    def close(self):
+        if getattr(self, 'b', None):
+            self.lib.lbm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -185,39 +185,59 @@ def config3(**kw):
     return sphere_case(mach=0.5, reynolds=300.0, T_wall_ratio=1.5, **kw)
 
 
-def batched_cases(count=64, seed0=1000, steps=2000):
-    """Uneven 2D ellipse cases: M ~ U{64..256}, nx = 4M, ny = nx/2, aspect U[1,4], angle U[0,90 deg],
-    Ma U[0.1,0.5], Re U[20,200] on L = 2a, isothermal T_w U[1,1.5] T_inf."""
+def conduction_number(case):
+    """kappa = lambda / (rho C_v) in lattice units: the explicit conduction update of the energy
+    equation needs kappa well below 1/(2D)."""
+    cv = R_GAS / (case.gamma - 1.0)
+    return case.lam / (case.rho_inf * cv)
+
+
+def batched_cases(count=64, seed0=1000, steps=2000, m_lo=64, m_hi=256, kappa_max=0.11, isothermal=False):
+    """Uneven 2D ellipse cases: M ~ U{m_lo..m_hi} (64..256), nx = 4M, ny = nx/2, aspect U[1,4],
+    angle U[0,90 deg], Ma U[0.1,0.5], Re U[20,200] on L = 2a, adiabatic no-slip wall (isothermal:
+    T_w U[1,1.5] T_inf, drawn in either case). (Ma, Re) pairs whose conduction number exceeds
+    kappa_max are drawn again (the explicit energy update is unstable there)."""
     cases = []
     for s in range(count):
         rng = np.random.Generator(np.random.PCG64(seed0 + s))
-        m = int(rng.integers(64, 257))
+        m = int(rng.integers(m_lo, m_hi + 1))
         aspect = rng.uniform(1.0, 4.0)
         angle = math.radians(rng.uniform(0.0, 90.0))
-        mach = rng.uniform(0.1, 0.5)
-        re = rng.uniform(20.0, 200.0)
         tw = rng.uniform(1.0, 1.5)
-        cases.append(ellipse_case(m, aspect, angle, mach, re, tw, steps=steps, name=f'batch{s}'))
+        while True:
+            mach = rng.uniform(0.1, 0.5)
+            re = rng.uniform(20.0, 200.0)
+            c = ellipse_case(m, aspect, angle, mach, re, tw if isothermal else None, steps=steps,
+                             name=f'batch{s}')
+            if conduction_number(c) <= kappa_max:
+                break
+        cases.append(c)
     return cases
 
 
-def ellipse_case(m, aspect, angle, mach, reynolds, T_wall_ratio, steps=2000, name='ellipse',
+def ellipse_case(m, aspect, angle, mach, reynolds, T_wall_ratio=None, steps=2000, name='ellipse',
                  nx=None, ny=None):
-    """Ellipse of perimeter m dx (one marker per cell), centre (0.3 nx, 0.5 ny)."""
+    """Ellipse of perimeter m dx (one marker per cell), centre (0.3 nx, 0.5 ny), no-slip wall.
+    T_wall_ratio None: adiabatic wall (dT/dn = 0) and T_inf = 1; otherwise an isothermal wall at
+    T_wall_ratio T_inf with T_ref = (T_inf + T_w)/2."""
     nx = nx if nx is not None else 4 * m
     ny = ny if ny is not None else nx // 2
     # perimeter(a, a/aspect) = m  ->  scale a unit-major ellipse
     per1 = ellipse_perimeter(1.0, 1.0 / aspect)
     a = m / per1
     b = a / aspect
-    T_inf, T_w = reference_temperatures(T_wall_ratio)
+    if T_wall_ratio is None:
+        T_inf = T_w = 1.0
+        kind, value = T_NEUMANN, 0.0
+    else:
+        T_inf, T_w = reference_temperatures(T_wall_ratio)
+        kind, value = T_DIRICHLET, T_w
     u, mu, lam = flow_units(mach, reynolds, 2.0 * a, T_inf)
     X, n = ellipse_markers((0.3 * nx, 0.5 * ny), a, b, angle, m)
-    kind = T_DIRICHLET if T_wall_ratio != 1.0 else T_DIRICHLET
     return Case(name=name, dim=2, dims=(nx, ny), mu=mu, lam=lam, u_inf=(u, 0.0), T_inf=T_inf,
                 ref_len=2.0 * a, ref_area=2.0 * a, surface=m, T_wall=T_w, steps=steps,
-                extra=dict(a=a, b=b, angle=angle, mach=mach, reynolds=reynolds),
-                **_markers_common(X, n, kind, T_w))
+                extra=dict(a=a, b=b, angle=angle, mach=mach, reynolds=reynolds, center=(0.3 * nx, 0.5 * ny)),
+                **_markers_common(X, n, kind, value))
 
 
 def random_state_perturbation(case, seed, amp_rho=1e-3, amp_u=None, amp_T=1e-3):
