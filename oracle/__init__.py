@@ -16,7 +16,8 @@ Modules
   ib       DIBM / FODIBM / FODIBM-R geometry, interpolation, target-value
            reconstruction, forces and spreading (Secs. 2.3-2.5)
   loads    drag / lift / Nusselt, boundary-condition errors, residual
-           (Secs. 3.2, 3.5 and the readings documented in the design doc)
+           (Secs. 3.2, 3.5; where the paper gives no formula, the reading is
+           stated in the function docstring)
 
 Every floating-point value is numpy float64. No blocking, fusion or reordering
 beyond what the paper's definitions state.

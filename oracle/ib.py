@@ -15,7 +15,7 @@ Follows Secs. 2.3-2.5 of the paper:
   Eqs. (30-32) FODIBM-R forces
   Sec. 2.5  order of the five sub-steps
 
-Readings (listed with the reasons in the design doc):
+Readings of the paper taken here:
   * Omega' is the closed interior: node i is inside iff (x_i - X_l*) . n_l* <= 0
     where l* is the marker nearest to x_i (ties: lowest index); FP64, products
     and sums left to right.

@@ -215,6 +215,26 @@ def batched_cases(count=64, seed0=1000, steps=2000, m_lo=64, m_hi=256, kappa_max
     return cases
 
 
+def learned_cases(count, seed0=0, nx=256, ny=128, m=64, mach=(0.05, 0.15), reynolds=(15.0, 35.0),
+                  kappa_max=0.11):
+    """Cases of the learned warm start: one ellipse of perimeter m on nx x ny, seed s drawn from
+    PCG64(seed0 + s): aspect U[1,4], angle U[0,90 deg], Ma and Re uniform in the given ranges
+    (redrawn while the conduction number exceeds kappa_max), adiabatic no-slip wall."""
+    cases = []
+    for s in range(count):
+        rng = np.random.Generator(np.random.PCG64(seed0 + s))
+        aspect = rng.uniform(1.0, 4.0)
+        angle = math.radians(rng.uniform(0.0, 90.0))
+        while True:
+            ma = rng.uniform(*mach)
+            re = rng.uniform(*reynolds)
+            c = ellipse_case(m, aspect, angle, ma, re, None, nx=nx, ny=ny, name=f'learn{seed0 + s}')
+            if conduction_number(c) <= kappa_max:
+                break
+        cases.append(c)
+    return cases
+
+
 def ellipse_case(m, aspect, angle, mach, reynolds, T_wall_ratio=None, steps=2000, name='ellipse',
                  nx=None, ny=None):
     """Ellipse of perimeter m dx (one marker per cell), centre (0.3 nx, 0.5 ny), no-slip wall.
@@ -257,3 +277,16 @@ def random_state_perturbation(case, seed, amp_rho=1e-3, amp_u=None, amp_T=1e-3):
     u = np.stack([case.u_inf[a] + amp_u * smooth() for a in range(D)])
     T = case.T_inf * (1.0 + amp_T * smooth())
     return rho, u, T
+
+
+def init_params(shapes, seed):
+    """Seeded initial parameters of a convolutional network, flat in layer order: per layer
+    (cin, cout, taps) the weights [cout][taps][cin] drawn N(0, 2 / (taps cin)) (N(0, 1 / cin) for
+    the last layer) and zero biases [cout]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for k, (ci, co, t) in enumerate(shapes):
+        std = math.sqrt((1.0 if k == len(shapes) - 1 else 2.0) / (t * ci))
+        parts.append(rng.standard_normal(co * t * ci) * std)
+        parts.append(np.zeros(co))
+    return np.concatenate(parts)
