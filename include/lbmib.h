@@ -208,6 +208,25 @@ void lbm_batch_destroy(lbm_batch* b);
 /* Message of the last error of this batch (of the last failed lbm_batch_create if b is NULL). */
 const char* lbm_batch_last_error(lbm_batch* b);
 
+/* ---- Learned warm start helpers (2D handles; the network is declared in lbmib_nn.h) --------
+ * Ma = |u_inf| / sqrt(gamma R T_inf). Arrays are device FP32 [N][4], node = x + nx y. */
+
+/* Network input planes of the case: {SDF / sdf_scale, ma_n, re_n, body indicator}. SDF is the
+ * distance to the nearest marker, negative where (x - X_l) . n_l < 0 for that marker (inside).
+ * ma_n and re_n are the caller's normalised Mach and Reynolds numbers. Asynchronous.
+ * Errors: LBM_E_INVAL (3D handle, sdf_scale <= 0), LBM_E_HIP. */
+int lbm_learn_input(lbm_handle* h, double sdf_scale, double ma_n, double re_n, float* d_out);
+
+/* Normalised fields of the current state (force-free rho, u, T as lbm_fields):
+ * {(rho - rho_inf)/(rho_inf Ma^2), u_x/|u_inf|, u_y/|u_inf|, (T - T_inf)/(T_inf Ma^2)}.
+ * Uses the working area (not during steps). Asynchronous. */
+int lbm_learn_target(lbm_handle* h, float* d_out);
+
+/* Warm start: the state is set, as lbm_set_fields, to the equilibrium of the denormalised
+ * prediction d_pred (the inverse of lbm_learn_target's normalisation), zero force history.
+ * Synchronises. Errors: LBM_E_INVAL, LBM_E_HIP. */
+int lbm_learn_warm_start(lbm_handle* h, const float* d_pred);
+
 /* Release the handle (not the caller's workspace). */
 void lbm_destroy(lbm_handle* h);
 

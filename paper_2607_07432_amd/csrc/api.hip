@@ -74,6 +74,8 @@ size_t layout(const lbm_params& p, char* base, Dev* d) {
     o.u_wall = L.take<double>(mc * D);
     o.t_value = L.take<double>(mc);
     o.t_kind = L.take<int>(mc);
+    o.Xm = L.take<double>(mc * D);
+    o.nm = L.take<double>(mc * D);
     o.G = L.take<double>(mc * (D + 2));
     o.diag = L.take<double>(mc * 8);
     o.eps = L.take<double>(mc * 4);
@@ -331,6 +333,8 @@ int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal, 
     HIPCHK(h, up(h->d.u_wall, u_wall, (size_t)m * D * 8));
     HIPCHK(h, up(h->d.t_value, t_value, (size_t)m * 8));
     HIPCHK(h, up(h->d.t_kind, t_kind, (size_t)m * 4));
+    HIPCHK(h, up(h->d.Xm, X, (size_t)m * D * 8));
+    HIPCHK(h, up(h->d.nm, normal, (size_t)m * D * 8));
     HIPCHK(h, up(h->d.rows, G.rows.data(), G.rows.size() * 8));
     HIPCHK(h, up(h->d.row_ptr, rp.data(), rp.size() * 8));
     HIPCHK(h, up(h->d.col_marker, G.col_marker.data(), G.col_marker.size() * 8));

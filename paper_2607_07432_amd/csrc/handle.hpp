@@ -25,6 +25,7 @@ struct Dev {
     // markers
     long long *supp_ptr, *supp_node, *proj_ptr, *proj_node, *tw_ptr, *tw_node;
     double *supp_w, *proj_w, *tw_w, *phi, *dbv, *W, *u_wall, *t_value, *G, *diag, *eps;
+    double *Xm, *nm;   // marker positions and outward normals [m][D]
     int* t_kind;
     long long *rows, *row_ptr, *col_marker;
     double *col_s, *fib, *fE, *h2off, *h2off2;   // sparse history, ping-pong with the state

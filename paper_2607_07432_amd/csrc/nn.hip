@@ -1,0 +1,946 @@
+// Convolutional neural operator of the learned warm start: a five-level U-Net on NHWC bf16
+// activations with FP32 accumulation on the gfx950 matrix cores
+// (v_mfma_f32_16x16x32_bf16), its backward pass and an Adam update, all hand-written.
+//
+// Topology (channels per level 32, 64, 128, 256, 256; 3x3 convolutions with ReLU):
+//   encoder level l: conv(cin -> C_l), conv(C_l -> C_l) = s_l; 2x2 average pooling between levels
+//   bottleneck:      conv(256 -> 256), conv(256 -> 256)
+//   decoder level l: nearest 2x upsampling, concatenation [up, s_l], conv(. -> C_l), conv(C_l -> C_l)
+//   head:            1x1 convolution 32 -> 4 (no activation), FP32 output.
+// The network input has 4 planes, padded to 8 channels in memory (the padding channels are zero).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmib_nn.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int WAVE = 64;
+constexpr int CIN0 = 8;        // padded input channels
+constexpr int NIN = 4;         // real input planes
+constexpr int NOUT = 4;        // output planes
+constexpr int LEVELS = 5;
+constexpr int CH[LEVELS] = {32, 64, 128, 256, 256};
+
+// ---------------------------------------------------------------------------------------------
+// Convolution forward as an implicit GEMM: Y[p][co] = act(sum_k W[co][k] X^[k][p] + b[co]),
+// k = tap * cin + ci, X^[k][p] = X[p shifted by tap][ci] (zero outside the image).
+// One wavefront computes a (16 TM) x (16 TN) tile of (output channels) x (pixels); its operands
+// are read straight from global memory as 8 consecutive channels per lane (16-byte loads):
+// A lane l holds W[co][k .. k+7] with co = l % 16, k = 8 (l / 16) + 32 s; B lane l holds
+// X[pixel l % 16][k .. k+7]; the result lane l holds rows 4 (l / 16) + r of column l % 16.
+// X has pixel stride xstride; Y is written at Y[p ystride + yoff + co].
+// Requires cin, xstride % 8 == 0, cout % (16 TM) == 0, ystride, yoff % 4 == 0.
+template <int TM, int TN>
+__global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, int cin, int xstride,
+                                                  const __bf16* __restrict__ Wt, const float* __restrict__ bias, int cout,
+                                                  int taps, int H, int Wd, long long P, int relu, __bf16* __restrict__ Y,
+                                                  int ystride, int yoff) {
+    const int lane = threadIdx.x % WAVE;
+    const long long wave = (long long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int co_tiles = cout / (16 * TM);
+    const long long tiles = (long long)co_tiles * ((P + 16 * TN - 1) / (16 * TN));
+    if (wave >= tiles) return;
+    const int co0 = (int)(wave % co_tiles) * 16 * TM;
+    const long long p0 = (wave / co_tiles) * 16 * TN;
+    const int K = taps * cin;
+    const int HW = H * Wd;
+    int py[TN], px[TN];
+    long long pb[TN];
+    bool pv[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const long long p = p0 + j * 16 + lane % 16;
+        pv[j] = p < P;
+        const long long n = p / HW;
+        const int r = (int)(p - n * HW);
+        py[j] = r / Wd;
+        px[j] = r - py[j] * Wd;
+        pb[j] = n * HW;
+    }
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = {};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const int kk = k0 + (lane / 16) * 8;
+        const bool kv = kk < K;
+        const int tap = kv ? kk / cin : 0;
+        const int ci = kk - tap * cin;
+        const int dy = taps == 9 ? tap / 3 - 1 : 0;
+        const int dx = taps == 9 ? tap % 3 - 1 : 0;
+        bf16x8 a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+            a[i] = kv ? *reinterpret_cast<const bf16x8*>(Wt + (long long)(co0 + i * 16 + lane % 16) * K + kk) : zero;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int y = py[j] + dy, x = px[j] + dx;
+            const bool in = kv && pv[j] && y >= 0 && y < H && x >= 0 && x < Wd;
+            b[j] = in ? *reinterpret_cast<const bf16x8*>(X + (pb[j] + (long long)y * Wd + x) * xstride + ci) : zero;
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            if (!pv[j]) continue;
+            const int cb = co0 + i * 16 + (lane / 16) * 4;
+            const long long p = p0 + j * 16 + lane % 16;
+            bf16x4 o;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = acc[i][j][r] + (bias ? bias[cb + r] : 0.f);
+                if (relu) v = v > 0.f ? v : 0.f;
+                o[r] = (__bf16)v;
+            }
+            *reinterpret_cast<bf16x4*>(Y + p * ystride + yoff + cb) = o;
+        }
+}
+
+// Weight gradient, split over pixels: part[s][co][k] = sum_{p in split s} dY[p][co] X^[k][p].
+// GEMM with M = co, N = k, and the pixels as the reduction dimension: lane l holds dY at 8
+// consecutive pixels (one image row, since W % 8 == 0) for co = l % 16, and X^ at the same
+// pixels for k = l % 16. dY and X have pixel strides dystride and xstride.
+// Requires cout % (16 TM) == 0, P % 8 == 0, W % 8 == 0, split length % 32 == 0.
+template <int TM, int TN>
+__global__ void __launch_bounds__(256) k_conv_wgrad(const __bf16* __restrict__ dY, int cout, int dystride,
+                                                    const __bf16* __restrict__ X, int cin, int xstride, int taps, int H,
+                                                    int Wd, long long P, int split_len, int nsplit,
+                                                    float* __restrict__ part) {
+    const int lane = threadIdx.x % WAVE;
+    const long long wave = (long long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int K = taps * cin;
+    const int co_tiles = cout / (16 * TM), k_tiles = (K + 16 * TN - 1) / (16 * TN);
+    const long long tiles = (long long)co_tiles * k_tiles * nsplit;
+    if (wave >= tiles) return;
+    const int cot = (int)(wave % co_tiles);
+    const int kt = (int)((wave / co_tiles) % k_tiles);
+    const int s = (int)(wave / ((long long)co_tiles * k_tiles));
+    const int co0 = cot * 16 * TM, k0 = kt * 16 * TN;
+    const int HW = H * Wd;
+    int tap[TN], ci[TN];
+    bool kv[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int k = k0 + j * 16 + lane % 16;
+        kv[j] = k < K;
+        tap[j] = kv[j] ? k / cin : 0;
+        ci[j] = kv[j] ? k - tap[j] * cin : 0;
+    }
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const long long pbeg = (long long)s * split_len;
+    const long long pend = pbeg + split_len < P ? pbeg + split_len : P;
+    const __bf16 z = (__bf16)0.f;
+    for (long long q = pbeg; q < pend; q += 32) {
+        const long long p = q + (lane / 16) * 8;     // first of this lane's 8 pixels (same image row)
+        const bool pv = p < pend;
+        const long long n = p / HW;
+        const int r = (int)(p - n * HW);
+        const int y = r / Wd, x = r - (r / Wd) * Wd;
+        bf16x8 a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const __bf16* src = dY + p * dystride + co0 + i * 16 + lane % 16;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a[i][e] = pv ? src[(long long)e * dystride] : z;
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int dy = taps == 9 ? tap[j] / 3 - 1 : 0;
+            const int dx = taps == 9 ? tap[j] % 3 - 1 : 0;
+            const int yy = y + dy;
+            const bool rowin = pv && kv[j] && yy >= 0 && yy < H;
+            const __bf16* src = X + (n * HW + (long long)yy * Wd) * xstride + ci[j];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int xx = x + e + dx;
+                b[j][e] = (rowin && xx >= 0 && xx < Wd) ? src[(long long)xx * xstride] : z;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    float* out = part + (long long)s * cout * K;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            if (!kv[j]) continue;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int co = co0 + i * 16 + (lane / 16) * 4 + rr;
+                const int k = k0 + j * 16 + lane % 16;
+                out[(long long)co * K + k] = acc[i][j][rr];
+            }
+        }
+}
+
+// Fixed-order sum of the split partials into the FP32 gradient.
+__global__ void k_sum_splits(const float* __restrict__ part, int nsplit, long long n, float* __restrict__ g) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += part[(long long)k * n + i];
+    g[i] = s;
+}
+
+// Bias gradient: db[c] = sum_p dY[p][c], block partials over pixel ranges, then a fixed-order sum.
+constexpr int BG_PIX = 2048;
+__global__ void __launch_bounds__(256) k_bias_part(const __bf16* __restrict__ dY, int c, int stride, long long P,
+                                                   float* __restrict__ part) {
+    const long long p0 = (long long)blockIdx.y * BG_PIX;
+    const int ch = blockIdx.x * 64 + threadIdx.x % 64;
+    const int row = threadIdx.x / 64;
+    __shared__ float red[4][64];
+    float s = 0.f;
+    if (ch < c)
+        for (long long p = p0 + row; p < p0 + BG_PIX && p < P; p += 4) s += (float)dY[p * stride + ch];
+    red[row][threadIdx.x % 64] = s;
+    __syncthreads();
+    if (row == 0 && ch < c)
+        part[(long long)blockIdx.y * c + ch] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+}
+
+// W'[ci][8 - t][co] = W[co][t][ci]: backward data is the forward convolution of dY with W'.
+__global__ void k_flip(const __bf16* __restrict__ W, int cout, int cin, __bf16* __restrict__ Wf) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)cout * 9 * cin;
+    if (i >= n) return;
+    const int ci = (int)(i % cin);
+    const int t = (int)((i / cin) % 9);
+    const int co = (int)(i / (9LL * cin));
+    Wf[((long long)ci * 9 + (8 - t)) * cout + co] = W[i];
+}
+
+// dA[p][off + c] *= (A[p][off + c] > 0), c < C (in place on the gradient of a ReLU output).
+__global__ void k_relu_bwd(__bf16* __restrict__ dA, const __bf16* __restrict__ A, long long P, int C, int stride, int off) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * C) return;
+    const long long p = i / C;
+    const int c = (int)(i - p * C);
+    const long long o = p * stride + off + c;
+    if (!((float)A[o] > 0.f)) dA[o] = (__bf16)0.f;
+}
+
+// 2x2 average pooling of a channel slice: out[n][y][x][c] = mean of in[n][2y+i][2x+j][off + c].
+__global__ void k_pool(const __bf16* __restrict__ in, int stride, int off, int C, int B, int H, int Wd,
+                       __bf16* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int h = H / 2, w = Wd / 2;
+    const long long n_out = (long long)B * h * w * C;
+    if (i >= n_out) return;
+    const int c = (int)(i % C);
+    const long long q = i / C;
+    const int x = (int)(q % w), y = (int)((q / w) % h);
+    const long long n = q / ((long long)w * h);
+    const long long b = ((n * H + 2 * y) * Wd + 2 * x) * stride + off + c;
+    const float s = ((float)in[b] + (float)in[b + stride]) + ((float)in[b + (long long)Wd * stride] + (float)in[b + (long long)Wd * stride + stride]);
+    out[i] = (__bf16)(0.25f * s);
+}
+
+// Adjoint of the pooling, accumulated: dIn[n][2y+i][2x+j][off + c] += dOut[n][y][x][c] / 4.
+__global__ void k_pool_bwd(const __bf16* __restrict__ dOut, int C, int B, int H, int Wd, __bf16* __restrict__ dIn,
+                           int stride, int off) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n_in = (long long)B * H * Wd * C;
+    if (i >= n_in) return;
+    const int c = (int)(i % C);
+    const long long q = i / C;
+    const int x = (int)(q % Wd), y = (int)((q / Wd) % H);
+    const long long n = q / ((long long)Wd * H);
+    const float g = (float)dOut[((n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c];
+    const long long o = q * stride + off + c;
+    dIn[o] = (__bf16)((float)dIn[o] + 0.25f * g);
+}
+
+// Nearest 2x upsampling into a channel slice: out[n][y][x][off + c] = in[n][y/2][x/2][c].
+__global__ void k_up(const __bf16* __restrict__ in, int C, int B, int H, int Wd, __bf16* __restrict__ out, int stride,
+                     int off) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n_out = (long long)B * H * Wd * C;
+    if (i >= n_out) return;
+    const int c = (int)(i % C);
+    const long long q = i / C;
+    const int x = (int)(q % Wd), y = (int)((q / Wd) % H);
+    const long long n = q / ((long long)Wd * H);
+    out[q * stride + off + c] = in[((n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c];
+}
+
+// Adjoint of the upsampling: dIn[n][y][x][c] = sum of the four dOut[n][2y+i][2x+j][off + c].
+__global__ void k_up_bwd(const __bf16* __restrict__ dOut, int stride, int off, int C, int B, int H, int Wd,
+                         __bf16* __restrict__ dIn) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int h = H / 2, w = Wd / 2;
+    const long long n_in = (long long)B * h * w * C;
+    if (i >= n_in) return;
+    const int c = (int)(i % C);
+    const long long q = i / C;
+    const int x = (int)(q % w), y = (int)((q / w) % h);
+    const long long n = q / ((long long)w * h);
+    const long long b = ((n * H + 2 * y) * Wd + 2 * x) * stride + off + c;
+    const float s = ((float)dOut[b] + (float)dOut[b + stride]) + ((float)dOut[b + (long long)Wd * stride] + (float)dOut[b + (long long)Wd * stride + stride]);
+    dIn[i] = (__bf16)s;
+}
+
+// FP32 input planes [P][4] -> bf16 [P][8] (channels 4..7 zero).
+__global__ void k_pack_input(const float* __restrict__ in, long long P, __bf16* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * CIN0) return;
+    const long long p = i / CIN0;
+    const int c = (int)(i - p * CIN0);
+    out[i] = (__bf16)(c < NIN ? in[p * NIN + c] : 0.f);
+}
+
+// Head: out[p][o] = sum_c Wh[o][c] A[p][c] + bh[o], 1x1, FP32 output.
+__global__ void k_head_fwd(const __bf16* __restrict__ A, const float* __restrict__ Wh, const float* __restrict__ bh,
+                           long long P, float* __restrict__ out) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    float a[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) a[c] = (float)A[p * 32 + c];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+        float s = 0.f;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) s += Wh[o * 32 + c] * a[c];
+        out[p * NOUT + o] = s + bh[o];
+    }
+}
+
+// Head backward, data: dA[p][c] = sum_o Wh[o][c] dOut[p][o] (bf16).
+__global__ void k_head_dgrad(const float* __restrict__ Wh, const float* __restrict__ dOut, long long P,
+                             __bf16* __restrict__ dA) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    float g[NOUT];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) g[o] = dOut[p * NOUT + o];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+        float s = 0.f;
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) s += Wh[o * 32 + c] * g[o];
+        dA[p * 32 + c] = (__bf16)s;
+    }
+}
+
+// Head backward, parameters: per block of HEAD_PIX pixels, thread q < 132 sums
+// dWh[o][c] = sum_p dOut[p][o] A[p][c] (q = 32 o + c) or dbh[o] = sum_p dOut[p][o] (q = 128 + o).
+constexpr int HEAD_PIX = 1024;
+constexpr int HEAD_NP = NOUT * 32 + NOUT;
+__global__ void __launch_bounds__(256) k_head_wgrad(const __bf16* __restrict__ A, const float* __restrict__ dOut,
+                                                    long long P, float* __restrict__ part) {
+    const int q = threadIdx.x;
+    if (q >= HEAD_NP) return;
+    const long long p0 = (long long)blockIdx.x * HEAD_PIX;
+    const int o = q < NOUT * 32 ? q / 32 : q - NOUT * 32;
+    const int c = q < NOUT * 32 ? q % 32 : -1;
+    float s = 0.f;
+    for (long long p = p0; p < p0 + HEAD_PIX && p < P; ++p) {
+        const float g = dOut[p * NOUT + o];
+        s += c >= 0 ? g * (float)A[p * 32 + c] : g;
+    }
+    part[(long long)blockIdx.x * HEAD_NP + q] = s;
+}
+
+// Column sums of a [rows][n] FP32 array in fixed order: out[i] = sum_r part[r][i].
+__global__ void k_colsum(const float* __restrict__ part, int rows, int n, float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int r = 0; r < rows; ++r) s += part[(long long)r * n + i];
+    out[i] = s;
+}
+
+// Masked mean squared error over P pixels and 4 planes (mask NULL: all ones).
+// Block partials of sum(mask err^2) and sum(mask), then the final sums in FP64.
+constexpr int LOSS_PIX = 2048;
+__global__ void __launch_bounds__(256) k_loss_part(const float* __restrict__ out, const float* __restrict__ tgt,
+                                                   const float* __restrict__ mask, long long P, double* __restrict__ part) {
+    const long long p0 = (long long)blockIdx.x * LOSS_PIX;
+    __shared__ double r1[256], r2[256];
+    double s1 = 0, s2 = 0;
+    for (long long p = p0 + threadIdx.x; p < p0 + LOSS_PIX && p < P; p += 256) {
+        const double m = mask ? mask[p] : 1.0;
+        double e2 = 0;
+        for (int o = 0; o < NOUT; ++o) {
+            const double d = (double)out[p * NOUT + o] - (double)tgt[p * NOUT + o];
+            e2 += d * d;
+        }
+        s1 += m * e2;
+        s2 += m;
+    }
+    r1[threadIdx.x] = s1;
+    r2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+            r2[threadIdx.x] += r2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = r1[0];
+        part[2 * blockIdx.x + 1] = r2[0];
+    }
+}
+
+// loss[0] = sum(mask err^2) / (4 sum(mask)), loss[1] = 4 sum(mask).
+__global__ void __launch_bounds__(256) k_loss_final(const double* __restrict__ part, int nparts, double* __restrict__ loss) {
+    __shared__ double r1[256], r2[256];
+    double s1 = 0, s2 = 0;
+    for (int k = threadIdx.x; k < nparts; k += 256) {
+        s1 += part[2 * k];
+        s2 += part[2 * k + 1];
+    }
+    r1[threadIdx.x] = s1;
+    r2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            r1[threadIdx.x] += r1[threadIdx.x + s];
+            r2[threadIdx.x] += r2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double cnt = NOUT * r2[0];
+        loss[0] = cnt > 0 ? r1[0] / cnt : 0.0;
+        loss[1] = cnt;
+    }
+}
+
+// dOut = 2 mask (out - tgt) / count.
+__global__ void k_loss_grad(const float* __restrict__ out, const float* __restrict__ tgt, const float* __restrict__ mask,
+                            long long P, const double* __restrict__ loss, float* __restrict__ g) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * NOUT) return;
+    const double cnt = loss[1];
+    const float m = mask ? mask[i / NOUT] : 1.f;
+    g[i] = cnt > 0 ? (float)(2.0 * m * ((double)out[i] - (double)tgt[i]) / cnt) : 0.f;
+}
+
+// Adam on the FP32 master parameters; the bf16 copy of each conv weight is refreshed.
+__global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ g,
+                       long long n, float lr, float b1, float b2, float eps, float c1, float c2, float wd,
+                       const long long* __restrict__ bf_map, __bf16* __restrict__ bf) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1, vh = vi / c2;
+    const float t = theta[i] - lr * (mh / (sqrtf(vh) + eps) + wd * theta[i]);
+    theta[i] = t;
+    const long long b = bf_map[i];
+    if (b >= 0) bf[b] = (__bf16)t;
+}
+
+// FP32 master -> bf16 copies (after set_params).
+__global__ void k_to_bf(const float* __restrict__ theta, long long n, const long long* __restrict__ bf_map,
+                        __bf16* __restrict__ bf) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long b = bf_map[i];
+    if (b >= 0) bf[b] = (__bf16)theta[i];
+}
+
+inline unsigned blocks(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Host side: topology, buffers, and the forward / backward / update sequences.
+
+namespace {
+
+struct Layer {
+    int cin, cout, taps;
+    long long w_off, b_off;     // offsets in the flat FP32 parameter vector
+    long long bf_off;           // offset of the bf16 weight copy
+};
+
+struct Act {                    // one activation buffer (and its gradient) at one level
+    __bf16* a;
+    __bf16* g;
+    int c;
+};
+
+std::vector<Layer> topology() {
+    std::vector<Layer> L;
+    auto add = [&](int ci, int co, int taps) { L.push_back({ci, co, taps, 0, 0, 0}); };
+    int c = CIN0;
+    for (int l = 0; l < LEVELS; ++l) {          // encoder + bottleneck: 2 convs per level
+        add(c, CH[l], 9);
+        add(CH[l], CH[l], 9);
+        c = CH[l];
+    }
+    for (int l = LEVELS - 2; l >= 0; --l) {     // decoder: input = [up (channels of level l+1 output), s_l]
+        const int up = CH[l + 1];
+        add(up + CH[l], CH[l], 9);
+        add(CH[l], CH[l], 9);
+    }
+    add(CH[0], NOUT, 1);                        // head
+    long long off = 0, bf = 0;
+    for (auto& x : L) {
+        x.w_off = off;
+        off += (long long)x.cout * x.taps * x.cin;
+        x.b_off = off;
+        off += x.cout;
+        x.bf_off = bf;
+        bf += (long long)x.cout * x.taps * x.cin;
+    }
+    return L;
+}
+
+long long param_count() {
+    const auto L = topology();
+    return L.back().b_off + L.back().cout;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct nn_unet {
+    int B = 0, H = 0, W = 0;
+    hipStream_t stream = nullptr;
+    std::vector<Layer> L;
+    long long np = 0, nbf = 0;
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    __bf16* wbf = nullptr;          // bf16 weights, concatenated per layer
+    __bf16* wflip = nullptr;        // flipped weights of one layer (backward data)
+    long long* bf_map = nullptr;    // parameter index -> bf16 index or -1
+    float* split = nullptr;         // weight-gradient split partials
+    size_t split_floats = 0;
+    float* small = nullptr;         // bias / head partials
+    size_t small_floats = 0;
+    double* lossp = nullptr;        // loss partials
+    double* loss = nullptr;         // [2]
+    __bf16* in0 = nullptr;          // [P0][8]
+    Act enc_a[LEVELS]{}, pool[LEVELS]{}, cat[LEVELS - 1]{}, dec_a[LEVELS - 1]{}, dec_b[LEVELS - 1]{};
+    Act bott_b{};                   // bottleneck second conv output
+    float* out = nullptr;           // [P0][4] FP32 head output
+    float* dout = nullptr;          // [P0][4]
+    int last_b = 0;                 // batch of the last forward
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_nn_error;
+
+int nfail(nn_unet* u, int code, const std::string& msg) {
+    if (u)
+        u->err = msg;
+    else
+        g_nn_error = msg;
+    return code;
+}
+
+#define NCHK(u, call)                                                                                  \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) return nfail((u), NN_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t layout(nn_unet* u, int B, int H, int W, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = align_up(off);
+        char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const auto L = topology();
+    const long long np = L.back().b_off + L.back().cout;
+    long long nbf = 0;
+    for (auto& x : L) nbf += (long long)x.cout * x.taps * x.cin;
+    const long long P0 = (long long)B * H * W;
+    float* theta = (float*)take(np * 4);
+    float* m = (float*)take(np * 4);
+    float* v = (float*)take(np * 4);
+    float* grad = (float*)take(np * 4);
+    __bf16* wbf = (__bf16*)take(nbf * 2);
+    long long maxw = 0;
+    for (auto& x : L) maxw = std::max(maxw, (long long)x.cout * x.taps * x.cin);
+    __bf16* wflip = (__bf16*)take(maxw * 2);
+    long long* bf_map = (long long*)take(np * 8);
+    // split partials: at most 64 splits of the largest weight
+    const size_t split_floats = (size_t)64 * maxw;
+    float* split = (float*)take(split_floats * 4);
+    const size_t small_floats = (size_t)std::max<long long>((P0 + HEAD_PIX - 1) / HEAD_PIX * HEAD_NP,
+                                                            (P0 + BG_PIX - 1) / BG_PIX * 256);
+    float* small = (float*)take(small_floats * 4);
+    double* lossp = (double*)take(((P0 + LOSS_PIX - 1) / LOSS_PIX) * 2 * 8);
+    double* loss = (double*)take(2 * 8);
+    __bf16* in0 = (__bf16*)take(P0 * CIN0 * 2);
+    Act enc_a[LEVELS]{}, pool[LEVELS]{}, cat[LEVELS - 1]{}, dec_a[LEVELS - 1]{}, dec_b[LEVELS - 1]{}, bott{};
+    auto act = [&](long long P, int c) {
+        Act a;
+        a.c = c;
+        a.a = (__bf16*)take(P * c * 2);
+        a.g = (__bf16*)take(P * c * 2);
+        return a;
+    };
+    for (int l = 0; l < LEVELS; ++l) {
+        const long long P = (long long)B * (H >> l) * (W >> l);
+        enc_a[l] = act(P, CH[l]);
+        if (l > 0) pool[l] = act(P, CH[l - 1]);
+        if (l < LEVELS - 1) {
+            cat[l] = act(P, CH[l + 1] + CH[l]);
+            dec_a[l] = act(P, CH[l]);
+            dec_b[l] = act(P, CH[l]);
+        } else {
+            bott = act(P, CH[l]);
+        }
+    }
+    float* out = (float*)take(P0 * NOUT * 4);
+    float* dout = (float*)take(P0 * NOUT * 4);
+    if (u) {
+        u->L = L;
+        u->np = np;
+        u->nbf = nbf;
+        u->theta = theta;
+        u->m = m;
+        u->v = v;
+        u->grad = grad;
+        u->wbf = wbf;
+        u->wflip = wflip;
+        u->bf_map = bf_map;
+        u->split = split;
+        u->split_floats = split_floats;
+        u->small = small;
+        u->small_floats = small_floats;
+        u->lossp = lossp;
+        u->loss = loss;
+        u->in0 = in0;
+        for (int l = 0; l < LEVELS; ++l) {
+            u->enc_a[l] = enc_a[l];
+            u->pool[l] = pool[l];
+        }
+        for (int l = 0; l < LEVELS - 1; ++l) {
+            u->cat[l] = cat[l];
+            u->dec_a[l] = dec_a[l];
+            u->dec_b[l] = dec_b[l];
+        }
+        u->bott_b = bott;
+        u->out = out;
+        u->dout = dout;
+    }
+    return align_up(off);
+}
+
+// Layer indices in topology order.
+int enc_conv(int l, int k) { return 2 * l + k; }                        // k = 0, 1
+int dec_conv(int l, int k) { return 2 * LEVELS + 2 * (LEVELS - 2 - l) + k; }
+int head_layer() { return 2 * LEVELS + 2 * (LEVELS - 1); }
+
+hipError_t conv_fwd(nn_unet* u, const Layer& ly, const __bf16* X, int xstride, const __bf16* Wt, const float* bias,
+                    int relu, int B, int H, int W, __bf16* Y, int ystride, int yoff) {
+    const long long P = (long long)B * H * W;
+    constexpr int TM = 2, TN = 4;
+    if (ly.cout % (16 * TM) || ly.cin % 8 || xstride % 8 || ystride % 4 || yoff % 4) return hipErrorInvalidValue;
+    const long long tiles = (long long)(ly.cout / (16 * TM)) * ((P + 16 * TN - 1) / (16 * TN));
+    hipLaunchKernelGGL((k_conv_fwd<TM, TN>), dim3(blocks(tiles, 4)), dim3(256), 0, u->stream, X, ly.cin, xstride, Wt,
+                       bias, ly.cout, ly.taps, H, W, P, relu, Y, ystride, yoff);
+    return hipGetLastError();
+}
+
+// dW (into grad at w_off) and db (at b_off) of a 3x3 layer from dY [P] (stride dys) and its input X.
+hipError_t conv_wgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, const __bf16* X, int xs, int B, int H,
+                      int W) {
+    const long long P = (long long)B * H * W;
+    const int K = ly.taps * ly.cin;
+    constexpr int TM = 2, TN = 2;
+    if (ly.cout % (16 * TM) || W % 8 || P % 8) return hipErrorInvalidValue;
+    const long long wsz = (long long)ly.cout * K;
+    int nsplit = (int)std::min<long long>(64, std::max<long long>(1, P / 4096));
+    while ((size_t)nsplit * wsz > u->split_floats && nsplit > 1) --nsplit;
+    long long split_len = (P + nsplit - 1) / nsplit;
+    split_len = (split_len + 31) / 32 * 32;
+    nsplit = (int)((P + split_len - 1) / split_len);
+    const long long tiles = (long long)(ly.cout / (16 * TM)) * ((K + 16 * TN - 1) / (16 * TN)) * nsplit;
+    hipLaunchKernelGGL((k_conv_wgrad<TM, TN>), dim3(blocks(tiles, 4)), dim3(256), 0, u->stream, dY, ly.cout, dys, X,
+                       ly.cin, xs, ly.taps, H, W, P, (int)split_len, nsplit, u->split);
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(wsz)), dim3(256), 0, u->stream, (const float*)u->split, nsplit, wsz,
+                       u->grad + ly.w_off);
+    const int nb = (int)((P + BG_PIX - 1) / BG_PIX);
+    hipLaunchKernelGGL(k_bias_part, dim3((ly.cout + 63) / 64, nb), dim3(256), 0, u->stream, dY, ly.cout, dys, P,
+                       u->small);
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(ly.cout)), dim3(256), 0, u->stream, (const float*)u->small, nb, ly.cout,
+                       u->grad + ly.b_off);
+    return hipGetLastError();
+}
+
+// dX [P][cin] (stride dxs) of a 3x3 layer from dY (stride dys): forward convolution with the
+// flipped weights.
+hipError_t conv_dgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, int B, int H, int W, __bf16* dX, int dxs) {
+    const long long n = (long long)ly.cout * 9 * ly.cin;
+    hipLaunchKernelGGL(k_flip, dim3(blocks(n)), dim3(256), 0, u->stream, (const __bf16*)(u->wbf + ly.bf_off), ly.cout,
+                       ly.cin, u->wflip);
+    Layer t{ly.cout, ly.cin, 9, 0, 0, 0};
+    return conv_fwd(u, t, dY, dys, u->wflip, nullptr, 0, B, H, W, dX, dxs, 0);
+}
+
+hipError_t relu_bwd(nn_unet* u, __bf16* g, const __bf16* a, long long P, int C, int stride, int off) {
+    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks(P * C)), dim3(256), 0, u->stream, g, a, P, C, stride, off);
+    return hipGetLastError();
+}
+
+int forward(nn_unet* u, int B, const float* d_in, float* d_out) {
+    const int H = u->H, W = u->W;
+    const long long P0 = (long long)B * H * W;
+    hipLaunchKernelGGL(k_pack_input, dim3(blocks(P0 * CIN0)), dim3(256), 0, u->stream, d_in, P0, u->in0);
+    NCHK(u, hipGetLastError());
+    const __bf16* x = u->in0;
+    int xs = CIN0;
+    for (int l = 0; l < LEVELS; ++l) {
+        const int h = H >> l, w = W >> l;
+        const Layer& c0 = u->L[enc_conv(l, 0)];
+        const Layer& c1 = u->L[enc_conv(l, 1)];
+        if (l > 0) {
+            // pooled s_{l-1}: the skip slice of cat[l-1]
+            const Act& src = u->cat[l - 1];
+            const long long n = (long long)B * h * w * CH[l - 1];
+            hipLaunchKernelGGL(k_pool, dim3(blocks(n)), dim3(256), 0, u->stream, (const __bf16*)src.a, src.c, CH[l],
+                               CH[l - 1], B, 2 * h, 2 * w, u->pool[l].a);
+            NCHK(u, hipGetLastError());
+            x = u->pool[l].a;
+            xs = CH[l - 1];
+        }
+        NCHK(u, conv_fwd(u, c0, x, xs, u->wbf + c0.bf_off, u->theta + c0.b_off, 1, B, h, w, u->enc_a[l].a, CH[l], 0));
+        if (l < LEVELS - 1)
+            NCHK(u, conv_fwd(u, c1, u->enc_a[l].a, CH[l], u->wbf + c1.bf_off, u->theta + c1.b_off, 1, B, h, w,
+                             u->cat[l].a, u->cat[l].c, CH[l + 1]));
+        else
+            NCHK(u, conv_fwd(u, c1, u->enc_a[l].a, CH[l], u->wbf + c1.bf_off, u->theta + c1.b_off, 1, B, h, w,
+                             u->bott_b.a, CH[l], 0));
+    }
+    const __bf16* below = u->bott_b.a;      // output of the level below (l + 1)
+    for (int l = LEVELS - 2; l >= 0; --l) {
+        const int h = H >> l, w = W >> l;
+        const long long n = (long long)B * h * w * CH[l + 1];
+        hipLaunchKernelGGL(k_up, dim3(blocks(n)), dim3(256), 0, u->stream, below, CH[l + 1], B, h, w, u->cat[l].a,
+                           u->cat[l].c, 0);
+        NCHK(u, hipGetLastError());
+        const Layer& d0 = u->L[dec_conv(l, 0)];
+        const Layer& d1 = u->L[dec_conv(l, 1)];
+        NCHK(u, conv_fwd(u, d0, u->cat[l].a, u->cat[l].c, u->wbf + d0.bf_off, u->theta + d0.b_off, 1, B, h, w,
+                         u->dec_a[l].a, CH[l], 0));
+        NCHK(u, conv_fwd(u, d1, u->dec_a[l].a, CH[l], u->wbf + d1.bf_off, u->theta + d1.b_off, 1, B, h, w,
+                         u->dec_b[l].a, CH[l], 0));
+        below = u->dec_b[l].a;
+    }
+    const Layer& hd = u->L[head_layer()];
+    hipLaunchKernelGGL(k_head_fwd, dim3(blocks(P0)), dim3(256), 0, u->stream, (const __bf16*)u->dec_b[0].a,
+                       (const float*)(u->theta + hd.w_off), (const float*)(u->theta + hd.b_off), P0, u->out);
+    NCHK(u, hipGetLastError());
+    if (d_out) NCHK(u, hipMemcpyAsync(d_out, u->out, P0 * NOUT * 4, hipMemcpyDeviceToDevice, u->stream));
+    u->last_b = B;
+    return NN_OK;
+}
+
+int backward(nn_unet* u, const float* d_tgt, const float* d_mask, double* d_loss_out) {
+    const int B = u->last_b, H = u->H, W = u->W;
+    const long long P0 = (long long)B * H * W;
+    const int nl = (int)((P0 + LOSS_PIX - 1) / LOSS_PIX);
+    hipLaunchKernelGGL(k_loss_part, dim3(nl), dim3(256), 0, u->stream, (const float*)u->out, d_tgt, d_mask, P0, u->lossp);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, u->stream, (const double*)u->lossp, nl, u->loss);
+    hipLaunchKernelGGL(k_loss_grad, dim3(blocks(P0 * NOUT)), dim3(256), 0, u->stream, (const float*)u->out, d_tgt, d_mask,
+                       P0, (const double*)u->loss, u->dout);
+    NCHK(u, hipGetLastError());
+    if (d_loss_out) NCHK(u, hipMemcpyAsync(d_loss_out, u->loss, 2 * 8, hipMemcpyDeviceToDevice, u->stream));
+    // head
+    const Layer& hd = u->L[head_layer()];
+    const int nh = (int)((P0 + HEAD_PIX - 1) / HEAD_PIX);
+    hipLaunchKernelGGL(k_head_dgrad, dim3(blocks(P0)), dim3(256), 0, u->stream, (const float*)(u->theta + hd.w_off),
+                       (const float*)u->dout, P0, u->dec_b[0].g);
+    hipLaunchKernelGGL(k_head_wgrad, dim3(nh), dim3(256), 0, u->stream, (const __bf16*)u->dec_b[0].a,
+                       (const float*)u->dout, P0, u->small);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, u->stream, (const float*)u->small, nh, HEAD_NP,
+                       u->grad + hd.w_off);
+    NCHK(u, hipGetLastError());
+    // decoder, top level first
+    for (int l = 0; l < LEVELS - 1; ++l) {
+        const int h = H >> l, w = W >> l;
+        const long long P = (long long)B * h * w;
+        const Layer& d0 = u->L[dec_conv(l, 0)];
+        const Layer& d1 = u->L[dec_conv(l, 1)];
+        NCHK(u, relu_bwd(u, u->dec_b[l].g, u->dec_b[l].a, P, CH[l], CH[l], 0));
+        NCHK(u, conv_wgrad(u, d1, u->dec_b[l].g, CH[l], u->dec_a[l].a, CH[l], B, h, w));
+        NCHK(u, conv_dgrad(u, d1, u->dec_b[l].g, CH[l], B, h, w, u->dec_a[l].g, CH[l]));
+        NCHK(u, relu_bwd(u, u->dec_a[l].g, u->dec_a[l].a, P, CH[l], CH[l], 0));
+        NCHK(u, conv_wgrad(u, d0, u->dec_a[l].g, CH[l], u->cat[l].a, u->cat[l].c, B, h, w));
+        NCHK(u, conv_dgrad(u, d0, u->dec_a[l].g, CH[l], B, h, w, u->cat[l].g, u->cat[l].c));
+        // the upsampled part of the concatenation goes to the output of the level below
+        __bf16* gbelow = l + 1 < LEVELS - 1 ? u->dec_b[l + 1].g : u->bott_b.g;
+        const long long n = (long long)B * (h / 2) * (w / 2) * CH[l + 1];
+        hipLaunchKernelGGL(k_up_bwd, dim3(blocks(n)), dim3(256), 0, u->stream, (const __bf16*)u->cat[l].g, u->cat[l].c, 0,
+                           CH[l + 1], B, h, w, gbelow);
+        NCHK(u, hipGetLastError());
+    }
+    // bottleneck and encoder, deepest level first
+    for (int l = LEVELS - 1; l >= 0; --l) {
+        const int h = H >> l, w = W >> l;
+        const long long P = (long long)B * h * w;
+        const Layer& c0 = u->L[enc_conv(l, 0)];
+        const Layer& c1 = u->L[enc_conv(l, 1)];
+        __bf16 *ga, *aa;
+        int stride, off;
+        if (l == LEVELS - 1) {
+            ga = u->bott_b.g;
+            aa = u->bott_b.a;
+            stride = CH[l];
+            off = 0;
+        } else {
+            // skip slice of cat[l]: the decoder's part is there, the pooling path adds its part
+            ga = u->cat[l].g;
+            aa = u->cat[l].a;
+            stride = u->cat[l].c;
+            off = CH[l + 1];
+            const long long n = P * CH[l];
+            hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(n)), dim3(256), 0, u->stream, (const __bf16*)u->pool[l + 1].g,
+                               CH[l], B, h, w, ga, stride, off);
+            NCHK(u, hipGetLastError());
+        }
+        NCHK(u, relu_bwd(u, ga, aa, P, CH[l], stride, off));
+        NCHK(u, conv_wgrad(u, c1, ga + off, stride, u->enc_a[l].a, CH[l], B, h, w));
+        NCHK(u, conv_dgrad(u, c1, ga + off, stride, B, h, w, u->enc_a[l].g, CH[l]));
+        NCHK(u, relu_bwd(u, u->enc_a[l].g, u->enc_a[l].a, P, CH[l], CH[l], 0));
+        const __bf16* xin = l > 0 ? u->pool[l].a : u->in0;
+        const int xs = l > 0 ? CH[l - 1] : CIN0;
+        NCHK(u, conv_wgrad(u, c0, u->enc_a[l].g, CH[l], xin, xs, B, h, w));
+        if (l > 0) NCHK(u, conv_dgrad(u, c0, u->enc_a[l].g, CH[l], B, h, w, u->pool[l].g, CH[l - 1]));
+    }
+    return NN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+long long nn_unet_param_count(void) { return param_count(); }
+
+size_t nn_unet_workspace_bytes(int batch, int H, int W) {
+    if (batch < 1 || H < 16 || W < 128 || H % 16 || W % 128) return 0;
+    return layout(nullptr, batch, H, W, nullptr);
+}
+
+int nn_unet_create(int batch, int H, int W, void* ws, size_t bytes, void* stream, nn_unet** out) {
+    if (!out) return nfail(nullptr, NN_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (batch < 1 || H < 16 || W < 128 || H % 16 || W % 128)
+        return nfail(nullptr, NN_E_INVAL, "need batch >= 1, H a multiple of 16 and W a multiple of 128");
+    const size_t need = layout(nullptr, batch, H, W, nullptr);
+    if (!ws || bytes < need) return nfail(nullptr, NN_E_NOMEM, "workspace too small: need " + std::to_string(need));
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return nfail(nullptr, NN_E_INVAL, "workspace not 256-byte aligned");
+    nn_unet* u = new (std::nothrow) nn_unet();
+    if (!u) return nfail(nullptr, NN_E_NOMEM, "host allocation failed");
+    u->B = batch;
+    u->H = H;
+    u->W = W;
+    u->stream = (hipStream_t)stream;
+    layout(u, batch, H, W, (char*)ws);
+    std::vector<long long> map(u->np, -1);
+    for (size_t i = 0; i + 1 < u->L.size(); ++i) {      // the head stays FP32
+        const Layer& x = u->L[i];
+        const long long n = (long long)x.cout * x.taps * x.cin;
+        for (long long k = 0; k < n; ++k) map[x.w_off + k] = x.bf_off + k;
+    }
+    hipError_t e = hipMemcpy(u->bf_map, map.data(), map.size() * 8, hipMemcpyHostToDevice);
+    for (float* a : {u->theta, u->m, u->v, u->grad})
+        if (e == hipSuccess) e = hipMemsetAsync(a, 0, u->np * 4, u->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(u->wbf, 0, u->nbf * 2, u->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(u->stream);
+    if (e != hipSuccess) {
+        std::string m = hipGetErrorString(e);
+        delete u;
+        return nfail(nullptr, NN_E_HIP, "create: " + m);
+    }
+    *out = u;
+    return NN_OK;
+}
+
+int nn_unet_set_params(nn_unet* u, const float* params, int on_device) {
+    if (!u || !params) return NN_E_INVAL;
+    NCHK(u, hipMemcpyAsync(u->theta, params, u->np * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           u->stream));
+    NCHK(u, hipMemsetAsync(u->m, 0, u->np * 4, u->stream));
+    NCHK(u, hipMemsetAsync(u->v, 0, u->np * 4, u->stream));
+    hipLaunchKernelGGL(k_to_bf, dim3(blocks(u->np)), dim3(256), 0, u->stream, (const float*)u->theta, u->np,
+                       (const long long*)u->bf_map, u->wbf);
+    NCHK(u, hipGetLastError());
+    if (!on_device) NCHK(u, hipStreamSynchronize(u->stream));
+    return NN_OK;
+}
+
+int nn_unet_get_params(nn_unet* u, float* params, int on_device) {
+    if (!u || !params) return NN_E_INVAL;
+    NCHK(u, hipMemcpyAsync(params, u->theta, u->np * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           u->stream));
+    if (!on_device) NCHK(u, hipStreamSynchronize(u->stream));
+    return NN_OK;
+}
+
+int nn_unet_get_grads(nn_unet* u, float* grads, int on_device) {
+    if (!u || !grads) return NN_E_INVAL;
+    NCHK(u, hipMemcpyAsync(grads, u->grad, u->np * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           u->stream));
+    if (!on_device) NCHK(u, hipStreamSynchronize(u->stream));
+    return NN_OK;
+}
+
+int nn_unet_forward(nn_unet* u, int b, const float* d_in, float* d_out) {
+    if (!u || !d_in) return NN_E_INVAL;
+    if (b < 1 || b > u->B) return nfail(u, NN_E_INVAL, "batch outside [1, capacity]");
+    return forward(u, b, d_in, d_out);
+}
+
+int nn_unet_backward(nn_unet* u, const float* d_target, const float* d_mask, double* d_loss) {
+    if (!u || !d_target) return NN_E_INVAL;
+    if (u->last_b < 1) return nfail(u, NN_E_STATE, "no forward pass");
+    return backward(u, d_target, d_mask, d_loss);
+}
+
+int nn_unet_adam(nn_unet* u, double lr, double beta1, double beta2, double eps, int t, double weight_decay) {
+    if (!u || t < 1) return NN_E_INVAL;
+    const float c1 = (float)(1.0 - std::pow(beta1, t)), c2 = (float)(1.0 - std::pow(beta2, t));
+    hipLaunchKernelGGL(k_adam, dim3(blocks(u->np)), dim3(256), 0, u->stream, u->theta, u->m, u->v, (const float*)u->grad,
+                       u->np, (float)lr, (float)beta1, (float)beta2, (float)eps, c1, c2, (float)weight_decay,
+                       (const long long*)u->bf_map, u->wbf);
+    NCHK(u, hipGetLastError());
+    return NN_OK;
+}
+
+void nn_unet_destroy(nn_unet* u) { delete u; }
+
+const char* nn_unet_last_error(nn_unet* u) { return u ? u->err.c_str() : g_nn_error.c_str(); }
+
+}  // extern "C"

@@ -24,7 +24,11 @@ EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step',
            'lbm_set_fields', 'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts',
            'ib_geometry', 'ib_marker_state', 'lbm_destroy', 'lbm_last_error',
            'lbm_batch_workspace_bytes', 'lbm_batch_create', 'lbm_batch_step', 'lbm_batch_step_timed',
-           'lbm_batch_set_tile', 'lbm_batch_config', 'lbm_batch_destroy', 'lbm_batch_last_error']
+           'lbm_batch_set_tile', 'lbm_batch_config', 'lbm_batch_destroy', 'lbm_batch_last_error',
+           'lbm_learn_input', 'lbm_learn_target', 'lbm_learn_warm_start',
+           'nn_unet_param_count', 'nn_unet_workspace_bytes', 'nn_unet_create', 'nn_unet_set_params',
+           'nn_unet_get_params', 'nn_unet_get_grads', 'nn_unet_forward', 'nn_unet_backward', 'nn_unet_adam',
+           'nn_unet_destroy', 'nn_unet_last_error']
 
 
 class LbmError(RuntimeError):
@@ -94,6 +98,30 @@ def load_library(path=LIB_PATH):
     lib.lbm_batch_destroy.restype = None
     lib.lbm_batch_last_error.argtypes = [vp]
     lib.lbm_batch_last_error.restype = ctypes.c_char_p
+    fp = P(ctypes.c_float)
+    lib.lbm_learn_input.argtypes = [vp, d, d, d, vp]
+    lib.lbm_learn_target.argtypes = [vp, vp]
+    lib.lbm_learn_warm_start.argtypes = [vp, vp]
+    lib.nn_unet_param_count.argtypes = []
+    lib.nn_unet_param_count.restype = ctypes.c_longlong
+    lib.nn_unet_workspace_bytes.argtypes = [i, i, i]
+    lib.nn_unet_workspace_bytes.restype = ctypes.c_size_t
+    lib.nn_unet_create.argtypes = [i, i, i, vp, ctypes.c_size_t, vp, P(vp)]
+    lib.nn_unet_set_params.argtypes = [vp, vp, i]
+    lib.nn_unet_get_params.argtypes = [vp, vp, i]
+    lib.nn_unet_get_grads.argtypes = [vp, vp, i]
+    lib.nn_unet_forward.argtypes = [vp, i, vp, vp]
+    lib.nn_unet_backward.argtypes = [vp, vp, vp, vp]
+    lib.nn_unet_adam.argtypes = [vp, d, d, d, d, i, d]
+    lib.nn_unet_destroy.argtypes = [vp]
+    lib.nn_unet_destroy.restype = None
+    lib.nn_unet_last_error.argtypes = [vp]
+    lib.nn_unet_last_error.restype = ctypes.c_char_p
+    for name in ('lbm_learn_input', 'lbm_learn_target', 'lbm_learn_warm_start', 'nn_unet_create',
+                 'nn_unet_set_params', 'nn_unet_get_params', 'nn_unet_get_grads', 'nn_unet_forward',
+                 'nn_unet_backward', 'nn_unet_adam'):
+        getattr(lib, name).restype = i
+    del fp
     for name in ('lbm_init_grid', 'ib_set_markers', 'lbm_step', 'lbm_step_timed', 'ib_wall_loads', 'lbm_fields', 'lbm_set_fields',
                  'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts', 'ib_geometry',
                  'ib_marker_state', 'lbm_batch_create', 'lbm_batch_step', 'lbm_batch_step_timed',
@@ -262,6 +290,19 @@ class Solver:
         H2 = np.ascontiguousarray(H2, dtype=np.float64).ravel()
         self._check(self.lib.lbm_set_state(self.h, _dptr(f), _dptr(e), _dptr(H2)))
 
+    def learn_input(self, out, sdf_scale, ma_n, re_n):
+        """Network input planes [ny, nx, 4] (FP32 device tensor) of this case."""
+        self._check(self.lib.lbm_learn_input(self.h, float(sdf_scale), float(ma_n), float(re_n),
+                                             ctypes.c_void_p(out.data_ptr())))
+
+    def learn_target(self, out):
+        """Normalised fields [ny, nx, 4] (FP32 device tensor) of the current state."""
+        self._check(self.lib.lbm_learn_target(self.h, ctypes.c_void_p(out.data_ptr())))
+
+    def warm_start(self, pred):
+        """Set the state to the equilibrium of a normalised prediction [ny, nx, 4] (FP32 device)."""
+        self._check(self.lib.lbm_learn_warm_start(self.h, ctypes.c_void_p(pred.data_ptr())))
+
     def geometry(self):
         c = np.zeros(6, dtype=np.int64)
         self._check(self.lib.ib_geometry_counts(self.h, _llptr(c)))
@@ -354,6 +395,84 @@ class Batch:
         if getattr(self, 'b', None):
             self.lib.lbm_batch_destroy(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+NN_OK = 0
+
+
+class UNet:
+    """The neural operator of the learned warm start (batch capacity, H x W images) on one GPU."""
+
+    def __init__(self, batch, H, W, device='cuda:0', stream=None):
+        import torch
+        self.lib = load_library()
+        self.B, self.H, self.W = batch, H, W
+        self.device = torch.device(device)
+        self.n_params = int(self.lib.nn_unet_param_count())
+        nbytes = self.lib.nn_unet_workspace_bytes(batch, H, W)
+        if nbytes == 0:
+            raise LbmError(LBM_E_INVAL, 'invalid network size (H % 16, W % 128)')
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        u = ctypes.c_void_p()
+        rc = self.lib.nn_unet_create(batch, H, W, ctypes.c_void_p(ptr), nbytes,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(u))
+        if rc != NN_OK:
+            raise LbmError(rc, self.lib.nn_unet_last_error(None).decode())
+        self.u = u
+        self.loss_buf = torch.zeros(2, dtype=torch.float64, device=self.device)
+
+    def _check(self, rc):
+        if rc != NN_OK:
+            raise LbmError(rc, self.lib.nn_unet_last_error(self.u).decode())
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        assert theta.size == self.n_params
+        self._check(self.lib.nn_unet_set_params(self.u, ctypes.c_void_p(theta.ctypes.data), 0))
+
+    def get_params(self):
+        out = np.empty(self.n_params, np.float32)
+        self._check(self.lib.nn_unet_get_params(self.u, ctypes.c_void_p(out.ctypes.data), 0))
+        return out
+
+    def get_grads(self):
+        out = np.empty(self.n_params, np.float32)
+        self._check(self.lib.nn_unet_get_grads(self.u, ctypes.c_void_p(out.ctypes.data), 0))
+        return out
+
+    def forward(self, x, out=None):
+        """x: FP32 device tensor [b, H, W, 4]; returns (or fills) the FP32 output [b, H, W, 4]."""
+        import torch
+        b = x.shape[0]
+        if out is None:
+            out = torch.empty((b, self.H, self.W, 4), dtype=torch.float32, device=self.device)
+        self._check(self.lib.nn_unet_forward(self.u, b, ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def backward(self, target, mask=None):
+        """Gradient of the masked MSE of the last forward; returns the device loss buffer {L, count}."""
+        mp = ctypes.c_void_p(mask.data_ptr()) if mask is not None else None
+        self._check(self.lib.nn_unet_backward(self.u, ctypes.c_void_p(target.data_ptr()), mp,
+                                              ctypes.c_void_p(self.loss_buf.data_ptr())))
+        return self.loss_buf
+
+    def adam(self, lr, t, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        self._check(self.lib.nn_unet_adam(self.u, float(lr), float(beta1), float(beta2), float(eps), int(t),
+                                          float(weight_decay)))
+
+    def close(self):
+        if getattr(self, 'u', None):
+            self.lib.nn_unet_destroy(self.u)
+            self.u = None
 
     def __del__(self):
         try:

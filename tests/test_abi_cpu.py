@@ -10,13 +10,17 @@ import pytest
 
 from paper_2607_07432_amd import lbmib, workloads
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 'include', 'lbmib.h')
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 'include')
+HEADERS = [os.path.join(INCLUDE, h) for h in ('lbmib.h', 'lbmib_nn.h')]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)
-    return sorted(set(re.findall(r'\b((?:lbm|ib)_[a-z_0-9]+)\s*\(', text)))
+    names = set()
+    for path in HEADERS:
+        text = open(path).read()
+        text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)
+        names |= set(re.findall(r'\b((?:lbm|ib|nn)_[a-z_0-9]+)\s*\(', text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -60,3 +64,13 @@ def test_binding_fails_loudly_without_library(tmp_path):
             lbmib.load_library(str(tmp_path / 'missing.so'))
     finally:
         lbmib._lib = saved
+
+
+def test_network_size_functions_are_pure():
+    from oracle import unet
+    lib = lbmib.load_library()
+    assert lib.nn_unet_param_count() == unet.param_count()
+    assert lib.nn_unet_workspace_bytes(4, 128, 256) > 0
+    assert lib.nn_unet_workspace_bytes(4, 120, 256) == 0      # H % 16
+    assert lib.nn_unet_workspace_bytes(4, 128, 200) == 0      # W % 128
+    assert lib.nn_unet_workspace_bytes(0, 128, 256) == 0

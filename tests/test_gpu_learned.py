@@ -1,0 +1,171 @@
+"""Learned warm start on the GPU (through the C ABI) against the FP64 references.
+
+  * grid helpers: input planes (signed distance, parameters, body indicator), normalised
+    targets, the warm-start state;
+  * the U-Net: forward against the reference with bf16 rounding emulated at the same points,
+    parameter gradients against the exact FP64 backward, one Adam step, and a short fit.
+The network runs in bf16 with FP32 accumulation, so its bars are relative L2 errors derived
+from the bf16 unit roundoff (2^-8): forward 1e-2, gradients 5e-2 per layer.
+"""
+import numpy as np
+import pytest
+
+from oracle import unet as U
+from oracle import warmstart as WS
+from paper_2607_07432_amd import workloads as wl
+
+from parity_util import rel
+
+pytestmark = pytest.mark.gpu
+
+H, W, B = 32, 128, 2
+
+
+@pytest.fixture(scope='module')
+def lbmib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip('no GPU')
+    from paper_2607_07432_amd import lbmib as mod
+    mod.load_library()
+    return mod
+
+
+def small_case(seed=0):
+    return wl.learned_cases(1, seed0=seed, nx=128, ny=64)[0]
+
+
+def relL2(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_learn_input_matches_reference(lbmib):
+    import torch
+    c = small_case(3)
+    s = lbmib.Solver.from_case(c, precision=lbmib.F64)
+    out = torch.zeros((64, 128, 4), dtype=torch.float32, device='cuda')
+    s.learn_input(out, 16.0, 0.25, -0.5)
+    got = out.cpu().numpy()
+    ref = WS.input_planes(128, 64, c.X, c.n, 16.0, 0.25, -0.5)
+    print('sdf rel', rel(got[..., 0], ref[..., 0]), flush=True)
+    assert rel(got[..., 0], ref[..., 0]) <= 1e-6
+    assert np.all(got[..., 1] == np.float32(0.25)) and np.all(got[..., 2] == np.float32(-0.5))
+    assert np.array_equal(got[..., 3], ref[..., 3].astype(np.float32))
+    assert got[..., 3].sum() > 10          # the body covers some nodes
+
+
+def test_learn_target_and_warm_start(lbmib):
+    import torch
+    c = small_case(4)
+    s = lbmib.Solver.from_case(c, precision=lbmib.F64)
+    s.step(25)
+    rho, u, T, _ = s.fields()
+    tgt = torch.zeros((64, 128, 4), dtype=torch.float32, device='cuda')
+    s.learn_target(tgt)
+    ref = WS.normalise(rho, u, T, c.rho_inf, np.array(c.u_inf), c.T_inf, c.gamma)
+    print('target rel', rel(tgt.cpu().numpy(), ref), flush=True)
+    assert rel(tgt.cpu().numpy(), ref) <= 1e-6
+    # warm start from a smooth prediction: the state's fields are the denormalised prediction
+    rng = np.random.Generator(np.random.PCG64(8))
+    pred = ref + 0.05 * rng.standard_normal(ref.shape)
+    pt = torch.tensor(pred.astype(np.float32), device='cuda')
+    s.warm_start(pt)
+    r2, u2, T2, _ = s.fields()
+    er, eu, eT = WS.denormalise(pt.cpu().numpy().astype(np.float64), c.rho_inf, np.array(c.u_inf), c.T_inf, c.gamma)
+    assert rel(r2, er) <= 1e-12 and rel(u2, eu) <= 1e-12 and rel(T2, eT) <= 1e-12
+    f, e, H2 = s.get_state()
+    assert np.all(H2 == 0.0)
+
+
+@pytest.fixture(scope='module')
+def net_case():
+    rng = np.random.Generator(np.random.PCG64(11))
+    theta = wl.init_params(U.layer_shapes(), seed=12)
+    theta[np.abs(theta) < 1e-30] = 0.0
+    theta = theta + 0.01 * rng.standard_normal(theta.shape) * (np.abs(theta) > 0)   # keep biases 0
+    theta = theta.astype(np.float32).astype(np.float64)
+    x = rng.standard_normal((B, H, W, 4)).astype(np.float32).astype(np.float64)
+    tgt = rng.standard_normal((B, H, W, 4)).astype(np.float32).astype(np.float64)
+    mask = (rng.uniform(size=(B, H, W)) > 0.1).astype(np.float64)
+    return theta, x, tgt, mask
+
+
+@pytest.fixture(scope='module')
+def gpu_net(lbmib, net_case):
+    import torch
+    theta, x, tgt, mask = net_case
+    net = lbmib.UNet(B, H, W)
+    assert net.n_params == U.param_count()
+    net.set_params(theta)
+    xt = torch.tensor(x.astype(np.float32), device='cuda')
+    tt = torch.tensor(tgt.astype(np.float32), device='cuda')
+    mt = torch.tensor(mask.astype(np.float32), device='cuda')
+    out = net.forward(xt)
+    loss = net.backward(tt, mt)
+    torch.cuda.synchronize()
+    return net, out.cpu().numpy(), loss.cpu().numpy(), net.get_grads(), (xt, tt, mt)
+
+
+def test_unet_forward_matches_reference(gpu_net, net_case):
+    theta, x, tgt, mask = net_case
+    _, out, _, _, _ = gpu_net
+    ref, _ = U.forward(theta, x, emulate_bf16=True)
+    e = relL2(out, ref)
+    print('forward rel L2', e, 'scale', np.abs(ref).max(), flush=True)
+    assert e <= 1e-2
+
+
+def test_unet_gradients_match_reference(gpu_net, net_case):
+    theta, x, tgt, mask = net_case
+    _, out, loss, g_gpu, _ = gpu_net
+    ref_out, cache = U.forward(theta, x, emulate_bf16=True)
+    g_ref, L_ref = U.backward(theta, cache, ref_out, tgt, mask)
+    print('loss', loss[0], L_ref, flush=True)
+    assert abs(loss[0] - L_ref) <= 1e-2 * L_ref
+    assert loss[1] == 4 * mask.sum()
+    off = 0
+    worst = 0.0
+    for k, (ci, co, t) in enumerate(U.layer_shapes()):
+        n = co * t * ci + co
+        a, b = g_gpu[off:off + n], g_ref[off:off + n]
+        if k == 0:                                    # padded input channels carry no gradient
+            Wg = a[:co * t * ci].reshape(co, t, ci)
+            assert np.all(Wg[..., U.NIN:] == 0.0)
+        e = relL2(a, b)
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+        worst = max(worst, e)
+        print(f'layer {k} ({ci}->{co}x{t}): grad rel L2 {e:.3e} cos {cos:.6f}', flush=True)
+        assert e <= 5e-2 and cos >= 0.998
+        off += n
+    assert off == U.param_count()
+
+
+def test_adam_step_matches_reference(lbmib, gpu_net):
+    net, _, _, g, _ = gpu_net
+    theta0 = net.get_params().astype(np.float64)
+    net.adam(1e-3, 1, weight_decay=1e-4)
+    theta1 = net.get_params().astype(np.float64)
+    ref, _, _ = U.adam_step(theta0, np.zeros_like(theta0), np.zeros_like(theta0), g.astype(np.float64), 1,
+                            lr=1e-3, wd=1e-4)
+    assert np.max(np.abs(theta1 - ref)) <= 1e-6 * max(1.0, np.abs(ref).max())
+
+
+def test_short_fit_reduces_loss(lbmib, net_case):
+    import torch
+    theta, x, tgt, _ = net_case
+    net = lbmib.UNet(B, H, W)
+    net.set_params(theta)
+    xt = torch.tensor(x.astype(np.float32), device='cuda')
+    # a smooth target the network can fit
+    yy, xx = np.mgrid[0:H, 0:W] / 16.0
+    smooth = np.stack([np.sin(xx + yy), np.cos(xx), 0.5 * np.sin(yy), xx * 0.1], axis=-1)
+    tt = torch.tensor(np.broadcast_to(smooth, (B, H, W, 4)).astype(np.float32).copy(), device='cuda')
+    losses = []
+    for it in range(1, 41):
+        net.forward(xt)
+        losses.append(float(net.backward(tt)[0].item()))
+        net.adam(1e-3, it)
+    print('losses', losses[0], losses[-1], flush=True)
+    assert np.isfinite(losses).all() and losses[-1] < 0.5 * losses[0]
