@@ -195,6 +195,11 @@ int lbm_batch_step(lbm_batch* b, int n);
  * forces, [1] spreading, [2] sweep, each the average per step over all cases. Synchronises. */
 int lbm_batch_step_timed(lbm_batch* b, int n, double* kernel_ms);
 
+/* Residual of every case after its last step (as lbm_residual; NaN for a case whose state held
+ * a non-finite value), out[n] on the host, in the order of creation. Synchronises.
+ * Errors: LBM_E_STATE (a case has taken no step), LBM_E_HIP. */
+int lbm_batch_residuals(lbm_batch* b, double* out);
+
 /* Use tile width tile_x (62, 126 or 254 nodes) and chunks of `chunk` rows (>= 1) for the sweep.
  * Errors: LBM_E_INVAL (other values), LBM_E_HIP. */
 int lbm_batch_set_tile(lbm_batch* b, int tile_x, int chunk);
@@ -223,8 +228,11 @@ int lbm_learn_input(lbm_handle* h, double sdf_scale, double ma_n, double re_n, f
 int lbm_learn_target(lbm_handle* h, float* d_out);
 
 /* Warm start: the state is set, as lbm_set_fields, to the equilibrium of the denormalised
- * prediction d_pred (the inverse of lbm_learn_target's normalisation), zero force history.
- * Synchronises. Errors: LBM_E_INVAL, LBM_E_HIP. */
+ * prediction d_pred (the inverse of lbm_learn_target's normalisation), zero force history, and
+ * the populations get the second-order non-equilibrium part w_i H_i : Pi / (2 c_s^4) with
+ * Pi = -rho c_s^2 tau_bar (grad u + grad u^T - div u I) (periodic central differences), the
+ * stress the finite-difference branch of Eq. (A.7) gives the predicted velocity; mass, momentum
+ * and energy are those of the prediction. Synchronises. Errors: LBM_E_INVAL, LBM_E_HIP. */
 int lbm_learn_warm_start(lbm_handle* h, const float* d_pred);
 
 /* Release the handle (not the caller's workspace). */

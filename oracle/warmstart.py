@@ -9,7 +9,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   * normalised fields with Ma = |u_inf| / sqrt(gamma R T_inf):
     {(rho - rho_inf)/(rho_inf Ma^2), u_x/|u_inf|, u_y/|u_inf|, (T - T_inf)/(T_inf Ma^2)}
     and the inverse map used for the warm start;
-  * the warm-start state: equilibrium populations of the denormalised fields (Eq. (A.3)).
+  * the warm-start state: equilibrium populations of the denormalised fields (Eq. (A.3)) plus
+    w_i H_i : Pi / (2 c_s^4) with Pi = -rho c_s^2 tau_bar S(u), S the deviatoric strain of the
+    finite-difference branch of Eq. (A.7) (tau_bar = mu / (rho c_s^2) + 1/2).
 The paper has no warm start; parity is pinned by closed forms (circle distance, free stream)
 and round trips in the tests.
 """
@@ -69,3 +71,18 @@ def denormalise(pred, rho_inf, u_inf, T_inf, gamma):
     u = np.stack([ur * pred[..., 1], ur * pred[..., 2]])
     T = T_inf * (1.0 + m2 * pred[..., 3])
     return rho, u, T
+
+
+def warm_state(lat, prm, rho, u, T):
+    """Populations f-bar of the warm start (2D): Eq. (A.3) plus the second-order part."""
+    from oracle import lbm as olbm
+    D, cs2 = lat.D, lat.cs2
+    feq = olbm.equilibrium(lat, rho, u, T)
+    du = olbm.central_gradient(u, D)
+    div = sum(du[a, a] for a in range(D))
+    eye = np.eye(D).reshape((D, D) + (1,) * rho.ndim)
+    strain = du + du.transpose((1, 0) + tuple(range(2, du.ndim))) - (2.0 / D) * eye * div
+    taubar = prm.mu / (rho * cs2) + 0.5
+    Pi = -rho * cs2 * taubar * strain
+    w = lat.w.reshape((-1,) + (1,) * rho.ndim)
+    return feq + w * np.einsum('iab,ab...->i...', lat.h2, Pi) / (2 * cs2 ** 2)

@@ -112,7 +112,22 @@ __global__ void __launch_bounds__(RTPB) k_residual_batch_final(const CaseDesc<S>
     }
 }
 
+// out[c] = residual of case c, NaN if its state held a non-finite value.
+template <class S>
+__global__ void k_gather_resid(const CaseDesc<S>* __restrict__ cases, int ncases, double* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncases) return;
+    const double* r = cases[c].resid;
+    out[c] = r[1] != 0.0 ? __builtin_nan("") : r[0];
+}
+
 }  // namespace
+
+template <class S>
+hipError_t launch_gather_resid(const CaseDesc<S>* cases, int ncases, double* out, hipStream_t st) {
+    hipLaunchKernelGGL((k_gather_resid<S>), dim3((ncases + 255) / 256), dim3(256), 0, st, cases, ncases, out);
+    return hipGetLastError();
+}
 
 template <class L, class S>
 hipError_t launch_residual_batch(const CaseDesc<S>* cases, int ncases, int total_parts, double* partials, int g,
@@ -135,6 +150,7 @@ struct lbm_batch {
     hipStream_t cap = nullptr;         // private stream the graphs are captured on
     char* desc = nullptr;              // device table of CaseDesc
     double* partials = nullptr;
+    double* resid = nullptr;           // [ncases] gathered residuals
     int total_items = 0, total_markers = 0, total_rows = 0, total_parts = 0;
     int tx = 62, chunk = 32, grid = 0;
     int gpar = 0;                      // parity of the next batch step
@@ -388,7 +404,7 @@ size_t lbm_batch_workspace_bytes(lbm_handle* const* cases, int n) {
     if (validate_cases(cases, n, why) != LBM_OK) return 0;
     size_t parts = 0;
     for (int c = 0; c < n; ++c) parts += (size_t)parts_of(cases[c]->N);
-    return align_up((size_t)n * desc_bytes()) + align_up(2 * parts * sizeof(double));
+    return align_up((size_t)n * desc_bytes()) + align_up(2 * parts * sizeof(double)) + align_up((size_t)n * sizeof(double));
 }
 
 int lbm_batch_create(lbm_handle* const* cases, int n, void* ws, size_t bytes, int tune, lbm_batch** out) {
@@ -407,6 +423,9 @@ int lbm_batch_create(lbm_handle* const* cases, int n, void* ws, size_t bytes, in
     b->stream = cases[0]->stream;
     b->desc = (char*)ws;
     b->partials = (double*)((char*)ws + align_up((size_t)n * desc_bytes()));
+    size_t parts = 0;
+    for (int c = 0; c < n; ++c) parts += (size_t)parts_of(cases[c]->N);
+    b->resid = (double*)((char*)b->partials + align_up(2 * parts * sizeof(double)));
     hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete b;
@@ -508,6 +527,24 @@ int lbm_batch_set_tile(lbm_batch* b, int tile_x, int chunk) {
     return by_precision(b, [&](auto S) {
         using ST = decltype(S);
         return rebuild<ST>(b, tile_x, chunk);
+    });
+}
+
+int lbm_batch_residuals(lbm_batch* b, double* out) {
+    if (!b || !out) return LBM_E_INVAL;
+    for (lbm_handle* h : b->hs)
+        if (!h->any_step) return bfail(b, LBM_E_STATE, "a case has taken no step");
+    const int n = (int)b->hs.size();
+    return by_precision(b, [&](auto S) {
+        using ST = decltype(S);
+        if (!in_sync<ST>(b)) {
+            const int rc = rebuild<ST>(b, b->tx, b->chunk);
+            if (rc != LBM_OK) return rc;
+        }
+        BCHK(b, launch_gather_resid<ST>(dtab<ST>(b), n, b->resid, b->stream));
+        BCHK(b, hipMemcpyAsync(out, b->resid, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        BCHK(b, hipStreamSynchronize(b->stream));
+        return (int)LBM_OK;
     });
 }
 

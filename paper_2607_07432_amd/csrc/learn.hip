@@ -1,7 +1,9 @@
 // Grid-side pieces of the learned warm start (2D): the network input planes of a case (signed
 // distance to the body, flow parameters, body indicator), the normalised steady fields used as
-// training targets, and the warm start itself (the state set to the equilibrium of the
-// denormalised prediction, Eq. (A.3)).
+// training targets, and the warm start itself: the equilibrium of the denormalised prediction
+// (Eq. (A.3)) plus the second-order non-equilibrium part that the finite-difference branch of
+// Eq. (A.7) assigns to its velocity field, Pi = -rho c_s^2 tau_bar (grad u + grad u^T - div u I),
+// so that the first collision sees the viscous stress of the prediction.
 //
 // Normalisation, with Ma = |u_inf| / sqrt(gamma R T_inf):
 //   t0 = (rho - rho_inf) / (rho_inf Ma^2), t1 = u_x / |u_inf|, t2 = u_y / |u_inf|,
@@ -73,6 +75,35 @@ __global__ void __launch_bounds__(TPB) k_learn_denorm(long long N, const float* 
     T[n] = T_inf * (1.0 + ma2 * (double)pred[4 * n + 3]);
 }
 
+// f_i += w_i H_i : Pi / (2 c_s^4) with Pi = -rho c_s^2 tau_bar S (D2Q9, periodic central differences).
+template <class S>
+__global__ void __launch_bounds__(TPB) k_learn_neq(int nx, int ny, const double* __restrict__ rho,
+                                                   const double* __restrict__ u, double mu, S* __restrict__ f) {
+    const long long N = (long long)nx * ny;
+    const long long n = (long long)blockIdx.x * TPB + threadIdx.x;
+    if (n >= N) return;
+    const int x = (int)(n % nx), y = (int)(n / nx);
+    const int xp = x + 1 < nx ? x + 1 : 0, xm = x > 0 ? x - 1 : nx - 1;
+    const int yp = y + 1 < ny ? y + 1 : 0, ym = y > 0 ? y - 1 : ny - 1;
+    const double* ux = u;
+    const double* uy = u + N;
+    const long long e = (long long)y * nx + xp, w = (long long)y * nx + xm;
+    const long long nn = (long long)yp * nx + x, s = (long long)ym * nx + x;
+    const double dxx = 0.5 * (ux[e] - ux[w]), dxy = 0.5 * (ux[nn] - ux[s]);   // d u_x / d x, d u_x / d y
+    const double dyx = 0.5 * (uy[e] - uy[w]), dyy = 0.5 * (uy[nn] - uy[s]);
+    const double div = dxx + dyy;
+    const double cs2 = 1.0 / 3.0;
+    const double r = rho[n];
+    const double coef = r * cs2 * (mu / (r * cs2) + 0.5);
+    const double P00 = -coef * (2.0 * dxx - div), P11 = -coef * (2.0 * dyy - div), P01 = -coef * (dxy + dyx);
+#pragma unroll
+    for (int i = 0; i < D2Q9::Q; ++i) {
+        const double cx = D2Q9::c[i][0], cy = D2Q9::c[i][1];
+        const double h = (cx * cx - cs2) * P00 + 2.0 * cx * cy * P01 + (cy * cy - cs2) * P11;
+        f[i * N + n] = S((double)f[i * N + n] + D2Q9::w[i] * h / (2.0 * cs2 * cs2));
+    }
+}
+
 int lfail(lbm_handle* h, int code, const std::string& m) {
     h->err = m;
     return code;
@@ -134,7 +165,24 @@ int lbm_learn_warm_start(lbm_handle* h, const float* d_pred) {
                        h->p.rho_inf, ur, h->p.T_inf, mach2_of(h), rho, u, T);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return lfail(h, LBM_E_HIP, std::string("learn_warm_start: ") + hipGetErrorString(e));
-    return lbm_set_fields(h, 1, rho, u, T);
+    const int rc = lbm_set_fields(h, 1, rho, u, T);
+    if (rc != LBM_OK) return rc;
+    // the current state is A when cur == 0
+    void* fcur = h->cur == 0 ? h->d.fA : h->d.fB;
+    const unsigned g = (unsigned)((N + TPB - 1) / TPB);
+    if (h->p.precision == LBM_F64)
+        hipLaunchKernelGGL(k_learn_neq<double>, dim3(g), dim3(TPB), 0, h->stream, h->p.nx, h->p.ny, (const double*)rho,
+                           (const double*)u, h->p.mu, (double*)fcur);
+    else
+        hipLaunchKernelGGL(k_learn_neq<float>, dim3(g), dim3(TPB), 0, h->stream, h->p.nx, h->p.ny, (const double*)rho,
+                           (const double*)u, h->p.mu, (float*)fcur);
+    const hipError_t e2 = hipGetLastError();
+    if (e2 == hipSuccess) {
+        const hipError_t e3 = hipStreamSynchronize(h->stream);
+        if (e3 != hipSuccess) return lfail(h, LBM_E_HIP, std::string("learn_warm_start: ") + hipGetErrorString(e3));
+        return LBM_OK;
+    }
+    return lfail(h, LBM_E_HIP, std::string("learn_warm_start: ") + hipGetErrorString(e2));
 }
 
 }  // extern "C"

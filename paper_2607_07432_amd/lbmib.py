@@ -24,7 +24,7 @@ EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step',
            'lbm_set_fields', 'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts',
            'ib_geometry', 'ib_marker_state', 'lbm_destroy', 'lbm_last_error',
            'lbm_batch_workspace_bytes', 'lbm_batch_create', 'lbm_batch_step', 'lbm_batch_step_timed',
-           'lbm_batch_set_tile', 'lbm_batch_config', 'lbm_batch_destroy', 'lbm_batch_last_error',
+           'lbm_batch_set_tile', 'lbm_batch_config', 'lbm_batch_residuals', 'lbm_batch_destroy', 'lbm_batch_last_error',
            'lbm_learn_input', 'lbm_learn_target', 'lbm_learn_warm_start',
            'nn_unet_param_count', 'nn_unet_workspace_bytes', 'nn_unet_create', 'nn_unet_set_params',
            'nn_unet_get_params', 'nn_unet_get_grads', 'nn_unet_forward', 'nn_unet_backward', 'nn_unet_adam',
@@ -94,6 +94,7 @@ def load_library(path=LIB_PATH):
     lib.lbm_batch_step_timed.argtypes = [vp, i, dp]
     lib.lbm_batch_config.argtypes = [vp, ip]
     lib.lbm_batch_set_tile.argtypes = [vp, i, i]
+    lib.lbm_batch_residuals.argtypes = [vp, dp]
     lib.lbm_batch_destroy.argtypes = [vp]
     lib.lbm_batch_destroy.restype = None
     lib.lbm_batch_last_error.argtypes = [vp]
@@ -125,7 +126,7 @@ def load_library(path=LIB_PATH):
     for name in ('lbm_init_grid', 'ib_set_markers', 'lbm_step', 'lbm_step_timed', 'ib_wall_loads', 'lbm_fields', 'lbm_set_fields',
                  'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts', 'ib_geometry',
                  'ib_marker_state', 'lbm_batch_create', 'lbm_batch_step', 'lbm_batch_step_timed',
-                 'lbm_batch_config', 'lbm_batch_set_tile'):
+                 'lbm_batch_config', 'lbm_batch_set_tile', 'lbm_batch_residuals'):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -381,15 +382,9 @@ class Batch:
     def residuals(self):
         """Residual of every case after the last batch step (nan for a case whose state holds a
         non-finite value)."""
-        out = []
-        for s in self.solvers:
-            try:
-                out.append(s.residual())
-            except LbmError as e:
-                if e.code != LBM_E_NONFINITE:
-                    raise
-                out.append(float('nan'))
-        return out
+        out = np.empty(len(self.solvers))
+        self._check(self.lib.lbm_batch_residuals(self.b, _dptr(out)))
+        return out.tolist()
 
     def close(self):
         if getattr(self, 'b', None):

@@ -84,6 +84,7 @@ def test_batch_matches_single_grid(lbmib, precision):
     # not bit-exact: tile widths are separate instantiations, whose FMA contraction may differ;
     # the bars are those of the single-grid path against the oracle
     tol = 1e-12 if prec == lbmib.F64 else 1e-5
+    gathered = batch.residuals()
     for k, (a, b) in enumerate(zip(ref, bat)):
         sa, sb = a.get_state(), b.get_state()
         err = state_rel(sb, sa)
@@ -94,6 +95,7 @@ def test_batch_matches_single_grid(lbmib, precision):
         assert err <= tol
         assert abs(la['Cd'] - lb['Cd']) <= (1e-10 if prec == lbmib.F64 else 1e-4) * max(1.0, abs(la['Cd']))
         assert abs(ra - rb) <= (1e-10 if prec == lbmib.F64 else 1e-4) * ra
+        assert gathered[k] == rb
     batch.close()
 
 

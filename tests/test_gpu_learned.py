@@ -77,6 +77,12 @@ def test_learn_target_and_warm_start(lbmib):
     assert rel(r2, er) <= 1e-12 and rel(u2, eu) <= 1e-12 and rel(T2, eT) <= 1e-12
     f, e, H2 = s.get_state()
     assert np.all(H2 == 0.0)
+    from oracle.lattice import for_dim
+    from parity_util import oracle_params
+    lat = for_dim(2)
+    fref = WS.warm_state(lat, oracle_params(c), er, eu, eT)
+    print('warm state rel', rel(f, fref), flush=True)
+    assert rel(f, fref) <= 1e-12
 
 
 @pytest.fixture(scope='module')
@@ -169,3 +175,30 @@ def test_short_fit_reduces_loss(lbmib, net_case):
         net.adam(1e-3, it)
     print('losses', losses[0], losses[-1], flush=True)
     assert np.isfinite(losses).all() and losses[-1] < 0.5 * losses[0]
+
+
+def test_trained_network_shortens_time_to_steady(lbmib):
+    """Train on the steady states the solver reaches from 200 seeds (128 x 64, ellipses of 32
+    markers), then march 8 held-out cases to r < 1e-7 from the warm and from the cold start."""
+    from paper_2607_07432_amd import learned
+    nx, ny, tol = 128, 64, 1e-7
+    orig = wl.learned_cases
+
+    def small(count, seed0=0, nx=256, ny=128, m=64, **kw):
+        return orig(count, seed0=seed0, nx=nx, ny=ny, m=32, **kw)
+
+    wl.learned_cases = small
+    try:
+        X, T, kept, _ = learned.generate(list(range(200)), nx, ny, tol, 40000, 250)
+        print('steady training cases', len(kept), flush=True)
+        assert len(kept) >= 100
+        net, hist, _, _ = learned.train(X, T, epochs=40, batch=8, lr=1e-3)
+        print('loss', hist[0], '->', hist[-1], flush=True)
+        assert hist[-1] < 0.2 * hist[0]
+        ev = learned.evaluate(net, list(range(10000, 10008)), nx, ny, tol, 40000, 250)
+    finally:
+        wl.learned_cases = orig
+    print(ev, flush=True)
+    assert ev['steady_both'] >= 3
+    assert ev['steps_warm_median'] < ev['steps_cold_median']
+    assert ev['pred_rel_l2_median'] < 0.5

@@ -134,3 +134,28 @@ def test_normalisation_of_free_stream_and_round_trip():
     assert np.allclose(WS.normalise(r2, u2, T2, rho_inf, u_inf, T_inf, gamma), q, atol=1e-12)
     m2 = WS.mach2(u_inf, T_inf, gamma)
     assert np.isclose(m2, 0.07 ** 2 / (1.4 / 3.0))
+
+
+def test_warm_state_moments_of_a_shear_flow():
+    """Zero-th and first moments are the fields' (the added part has none); the deviatoric second
+    moment of f - f^eq is -rho c_s^2 tau_bar S, here for u_x = g y: Pi_xy = -rho c_s^2 tau_bar g."""
+    from oracle.lattice import for_dim
+    from oracle import lbm as olbm
+    lat = for_dim(2)
+    ny, nx, g, mu = 12, 10, 1e-3, 0.05
+    prm = olbm.Params(mu=mu, lam=0.1, gamma=1.4, sigma=0.98, rho_inf=1.0, u_inf=(0.05, 0.0), T_inf=1.0,
+                      bc='periodic')
+    rho = np.full((ny, nx), 1.02)
+    T = np.full((ny, nx), 0.97)
+    u = np.zeros((2, ny, nx))
+    u[0] = g * np.arange(ny)[:, None]
+    f = WS.warm_state(lat, prm, rho, u, T)
+    feq = olbm.equilibrium(lat, rho, u, T)
+    cf = lat.c.astype(np.float64)
+    assert np.allclose(f.sum(0), rho, atol=1e-14)
+    assert np.allclose(np.einsum('ia,i...->a...', cf, f), rho * u, atol=1e-14)
+    Pi = olbm.deviatoric_second_moment(lat, f - feq)
+    inner = slice(1, ny - 1)                  # away from the periodic wrap of the linear profile
+    taubar = mu / (1.02 / 3.0) + 0.5
+    assert np.allclose(Pi[0, 1][inner], -1.02 / 3.0 * taubar * g, rtol=1e-12, atol=0)
+    assert np.allclose(Pi[0, 0][inner], 0.0, atol=1e-15) and np.allclose(Pi[1, 1][inner], 0.0, atol=1e-15)
