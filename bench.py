@@ -162,6 +162,27 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def bench_learned(args):
+    """Learned warm start on 256 x 128 ellipses: solver-generated steady data, training, and the
+    time to steady state (FP64, r < 1e-7) warm vs cold on held-out seeds."""
+    from paper_2607_07432_amd import learned
+    ev = learned.main(['--train', str(args.train_cases), '--heldout', str(args.heldout_cases),
+                       '--epochs', str(args.epochs)])
+    out = {
+        'metric': 'time-to-steady warm vs cold at L2 residual 1e-7 (FP64), 256x128 ellipses',
+        'value': round(ev['speedup_wall'], 4), 'unit': 'x (cold wall time / warm wall time incl. inference)',
+        'n_gpus': 1, 'steps': None, 'warmup': 0, 'ms_per_step': None, 'higher_is_better': True,
+        'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64 solver, bf16 network', 'data': 'synthetic',
+        'config': {'workload': f'learned: {args.train_cases} training seeds, {args.heldout_cases} held-out seeds, '
+                               f'{args.epochs} epochs, 5-level U-Net 32..256 channels'},
+        'roofline': {'bound': 'mfma', 'kernel': 'U-Net training step (forward + backward + Adam), batch 16',
+                     'achieved': round(ev['train_tflops'], 2), 'peak': 2500.0, 'unit': 'TFLOP/s',
+                     'frac': round(ev['train_tflops'] / 2500.0, 4), 'traffic': None},
+        'learned': ev,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -172,7 +193,10 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--copy-kernel', type=int, default=0)
     ap.add_argument('--sweep', choices=('fused', 'threepass'), default='fused')
-    ap.add_argument('--workload', choices=('sphere3d', 'batch64'), default='sphere3d')
+    ap.add_argument('--workload', choices=('sphere3d', 'batch64', 'learned'), default='sphere3d')
+    ap.add_argument('--train-cases', type=int, default=2000)
+    ap.add_argument('--heldout-cases', type=int, default=512)
+    ap.add_argument('--epochs', type=int, default=40)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -184,6 +208,9 @@ def main():
         return
     if args.workload == 'batch64':
         bench_batch(args)
+        return
+    if args.workload == 'learned':
+        bench_learned(args)
         return
 
     import torch
