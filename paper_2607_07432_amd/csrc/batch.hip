@@ -219,6 +219,8 @@ void fill_desc(lbm_batch* b, int tx, int chunk) {
         d.a[1] = h->args;
         d.a[1].rows.h2off = h->d.h2off2;
         d.a[1].rows.h2off_out = h->d.h2off;
+        d.k[0] = fused_args<S>(d.a[0]);
+        d.k[1] = fused_args<S>(d.a[1]);
         d.st[0] = stateA<S>(h);
         d.st[1] = stateB<S>(h);
         d.mk = h->mk;
@@ -228,7 +230,7 @@ void fill_desc(lbm_batch* b, int tx, int chunk) {
         d.cur0 = h->cur;
         d.tiles_x = (h->p.nx + tx - 1) / tx;
         d.chunk = chunk;
-        d.small = (h->p.nx < tx + 4 || h->p.ny < 8) ? 1 : 0;
+        d.small = (h->p.nx <= tx || h->p.ny < 4) ? 1 : 0;
         d.item0 = items;
         items += d.tiles_x * ((h->p.ny + chunk - 1) / chunk);
         d.marker0 = markers;

@@ -65,12 +65,39 @@ struct MarkersP {
     double* eps;            // [m][4]: eps_dir, eps_neu, eps_iso, kind mask
 };
 
+// Arguments of the fused sweep in its arithmetic type C (no conversions inside the kernel).
+template <class C>
+struct FusedK {
+    int nx, ny, nz, bc_x;
+    long long N;
+    GasT<C> gas;
+    C e_ref;
+    C fdev[19];
+    RowsP rows;
+};
+
+template <class C>
+inline FusedK<C> fused_args(const SweepArgs& a) {
+    FusedK<C> k;
+    k.nx = a.grid.nx;
+    k.ny = a.grid.ny;
+    k.nz = a.grid.nz;
+    k.bc_x = a.grid.bc_x;
+    k.N = a.grid.N;
+    k.gas = gas_as<C>(a.gas);
+    k.e_ref = C(a.fs.e_ref);
+    for (int i = 0; i < 19; ++i) k.fdev[i] = C(a.fs.fdev[i]);
+    k.rows = a.rows;
+    return k;
+}
+
 // One case of a batch of independent 2D grids (an entry of a device table). Index k of a[] and
 // st[] belongs to the step parity at which state k is the current one; at batch step parity g
 // the current state is (cur0 + g) & 1.
 template <class S>
 struct CaseDesc {
     SweepArgs a[2];         // a[k].rows.h2off / h2off_out: the history buffers when state k is current
+    FusedK<S> k[2];         // the same for the fused sweep
     StateP<S> st[2];        // state A, state B of the case
     MarkersP mk;
     int cur0;               // current state at batch parity 0

@@ -15,11 +15,19 @@
 
 namespace lbmib {
 
-struct Gas {
-    double mu, lambda_, gamma, sigma, Cv, Cp;
+// Gas and model constants in the arithmetic type R of the kernel that reads them.
+template <class R>
+struct GasT {
+    R mu, lambda_, gamma, sigma, Cv, Cp;
     int with_aC;
-    double inv_Cv;      // 1 / Cv
+    R inv_Cv;           // 1 / Cv
 };
+using Gas = GasT<double>;
+
+template <class C>
+__host__ __device__ inline GasT<C> gas_as(const Gas& g) {
+    return {C(g.mu), C(g.lambda_), C(g.gamma), C(g.sigma), C(g.Cv), C(g.Cp), g.with_aC, C(g.inv_Cv)};
+}
 
 template <class L, class C>
 struct Node {
@@ -112,8 +120,8 @@ struct Stencil {
 //   B = (rho u u u)^(3r) + (1 - 1/taubar) Pi^(3r).
 // The population part of Pi (Eq. (A.7)) uses the exact lattice moment
 // sum_i c c (f^eq_i - w_i) = rho u u + (rho theta - 1) cs^2 I, whose deviatoric part is dev(rho u u).
-template <class L, class C>
-__device__ __forceinline__ void collide(const Gas& g, const C* fd, const Node<L, C>& n, const Stencil<C>& s,
+template <class L, class C, class R>
+__device__ __forceinline__ void collide(const GasT<R>& g, const C* fd, const Node<L, C>& n, const Stencil<C>& s,
                                         const C* fib, const C (*H2)[3], C* fcol, C (*H2new)[3]) {
     constexpr int D = L::D;
     const C rho = n.rho;
@@ -159,7 +167,7 @@ __device__ __forceinline__ void collide(const Gas& g, const C* fd, const Node<L,
                 if (L::c[i][a] * L::c[i][b] != 0) M2[a][b] += C(L::c[i][a] * L::c[i][b]) * fd[i];
 
     // Eq. (A.7): Pi = sigma [dev(M2) - dev(rho u u) + H2/2] - (1 - sigma) rho cs^2 taubar S.
-    const C taubar = C(3.0 * g.mu) * n.inv_rho + C(0.5);   // tau = nu / cs^2, Eq. (6)
+    const C taubar = C(3) * C(g.mu) * n.inv_rho + C(0.5);   // tau = nu / cs^2, Eq. (6)
     const C om = C(1) - C(1) / taubar;
     C trP = 0;
 #pragma unroll
@@ -275,8 +283,8 @@ __device__ __forceinline__ void muscl_weights(C ua, C ub, C* w) {
 // with p' = p - cs^2, H = k + Cp T, h = Cp T, k = |u|^2/2, (.)_f the mean of cells 1 and 2.
 // By linearity of F* this is F*(Psi) + (h - k)_f Fr + sum_b u_b,f Fm_b - lambda (T_2 - T_1),
 // Psi = rho u_a (k + Cp T) - (h - k)_f rho u_a - sum_b u_b,f rho u_a u_b - u_a,f p'.
-template <class L, class C>
-__device__ __forceinline__ C energy_flux(const Gas& g, int a, const Cell<L, C>* c4, C Fr, const C* Fm) {
+template <class L, class C, class R>
+__device__ __forceinline__ C energy_flux(const GasT<R>& g, int a, const Cell<L, C>* c4, C Fr, const C* Fm) {
     constexpr int D = L::D;
     C k[4];
 #pragma unroll

@@ -76,19 +76,24 @@ struct FusedArgs {
 
 }  // namespace
 
-// One work item: the tile at (x0, y0) of planes [z0, z1) of one grid. small: a grid dimension
-// is smaller than a tile plus its halo (periodic indices by the general modulo).
-template <class L, class S, class C, int TX, int TY>
-__device__ __forceinline__ void fused_tile(const SweepArgs& a, StateP<S> A, StateP<S> B, int x0, int y0, int z0,
+// One work item: the tile at (x0, y0) of planes [z0, z1) of one grid. Periodic indices: SM = 0
+// by one conditional wrap (valid while a grid dimension exceeds the tile), SM = 1 by the general
+// modulo, SM = 2 as the runtime flag small says.
+template <class L, class S, class C, int TX, int TY, int SM>
+__device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, StateP<S> B, int x0, int y0, int z0,
                                            int z1, bool small, FusedSmem<L, S, C, TX, TY>& sm) {
     using G = FG<L, TX, TY>;
     constexpr int D = L::D;
-    const GridP& g = a.grid;
+    const FusedK<C>& g = a;
     const long long N = g.N;
     const int nm = D == 3 ? g.nz : g.ny;               // length of the marching axis
     const int t = threadIdx.x;
 
-    auto wr = [&](int v, int n) { return small ? wrapm(v, n) : wrap1(v, n); };
+    auto wr = [&](int v, int n) {
+        if (SM == 0) return wrap1(v, n);
+        if (SM == 1) return wrapm(v, n);
+        return small ? wrapm(v, n) : wrap1(v, n);
+    };
     auto gnode = [&](int x, int y, int m) -> long long {
         const int xw = wr(x, g.nx);
         if (D == 3) return (long long)xw + (long long)g.nx * ((long long)wr(y, g.ny) + (long long)g.ny * wr(m, nm));
@@ -136,7 +141,7 @@ __device__ __forceinline__ void fused_tile(const SweepArgs& a, StateP<S> A, Stat
             C uu = 0;
 #pragma unroll
             for (int b = 0; b < D; ++b) uu += (j[b] * ir) * (j[b] * ir);
-            const C T = ((C(pa_e[kk]) + C(a.fs.e_ref)) * ir - C(0.5) * uu) * C(a.gas.inv_Cv);
+            const C T = ((C(pa_e[kk]) + a.e_ref) * ir - C(0.5) * uu) * a.gas.inv_Cv;
             const int r = pa_r[kk];
             sm.mac[sl][0][k] = rho;
 #pragma unroll
@@ -412,7 +417,7 @@ __device__ __forceinline__ void fused_tile(const SweepArgs& a, StateP<S> A, Stat
         if (g.bc_x == 1) {
             if (xo < 2) {
 #pragma unroll
-                for (int i = 0; i < L::Q; ++i) B.f[i * N + n] = S(a.fs.fdev[i]);
+                for (int i = 0; i < L::Q; ++i) B.f[i * N + n] = S(a.fdev[i]);
                 B.e[n] = S(0);
                 continue;
             }
@@ -430,8 +435,8 @@ __device__ __forceinline__ void fused_tile(const SweepArgs& a, StateP<S> A, Stat
     }
 }
 
-template <class L, class S, class C, int TX, int TY>
-__global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(SweepArgs a, FusedArgs fa, StateP<S> A, StateP<S> B) {
+template <class L, class S, class C, int TX, int TY, int SM>
+__global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(FusedK<C> a, FusedArgs fa, StateP<S> A, StateP<S> B) {
     __shared__ FusedSmem<L, S, C, TX, TY> sm;
     constexpr int D = L::D;
     // XCD-aware placement: consecutive logical workgroups (neighbouring tiles) share an XCD.
@@ -443,10 +448,10 @@ __global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(S
     const int rem = logical % per_plane;
     const int x0 = (rem % fa.tiles_x) * TX;
     const int y0 = D == 3 ? (rem / fa.tiles_x) * TY : 0;
-    const int nm = D == 3 ? a.grid.nz : a.grid.ny;
+    const int nm = D == 3 ? a.nz : a.ny;
     const int z0 = chunk * fa.chunk;
     const int z1 = min(z0 + fa.chunk, nm);
-    fused_tile<L, S, C, TX, TY>(a, A, B, x0, y0, z0, z1, fa.small != 0, sm);
+    fused_tile<L, S, C, TX, TY, SM>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
 }
 
 // Persistent sweep over the work items of a batch of 2D grids. The items of one case are
@@ -473,9 +478,9 @@ __global__ void __launch_bounds__(TX + 2) k_fused_batch(const CaseDesc<S>* __res
         const int chunk = local / cd.tiles_x;
         const int x0 = (local % cd.tiles_x) * TX;
         const int z0 = chunk * cd.chunk;
-        const int z1 = min(z0 + cd.chunk, cd.a[0].grid.ny);
+        const int z1 = min(z0 + cd.chunk, cd.k[0].ny);
         __syncthreads();                              // the previous item's LDS reads are done
-        fused_tile<L, S, S, TX, 1>(cd.a[cur], cd.st[cur], cd.st[cur ^ 1], x0, 0, z0, z1, cd.small != 0, sm);
+        fused_tile<L, S, S, TX, 1, 2>(cd.k[cur], cd.st[cur], cd.st[cur ^ 1], x0, 0, z0, z1, cd.small != 0, sm);
     }
 }
 
@@ -514,10 +519,14 @@ hipError_t launch_fused_tile(const SweepArgs& a, StateP<S> A, StateP<S> B, int c
     fa.chunks = (nm + fa.chunk - 1) / fa.chunk;
     fa.total = fa.tiles_x * fa.tiles_y * fa.chunks;
     fa.per_xcd = (fa.total + 7) / 8;
-    fa.small = (g.nx < TX + 4) || (L::D == 3 && g.ny < TY + 4) || nm < 8;
+    fa.small = (g.nx <= TX) || (L::D == 3 && g.ny <= TY) || nm < 4;
     const int grid = fa.per_xcd * 8;
     constexpr int threads = (TX + 2) * (L::D == 3 ? TY + 2 : 1);
-    hipLaunchKernelGGL((k_fused<L, S, S, TX, TY>), dim3(grid), dim3(threads), 0, st, a, fa, A, B);
+    const FusedK<S> k = fused_args<S>(a);
+    if (fa.small)
+        hipLaunchKernelGGL((k_fused<L, S, S, TX, TY, 1>), dim3(grid), dim3(threads), 0, st, k, fa, A, B);
+    else
+        hipLaunchKernelGGL((k_fused<L, S, S, TX, TY, 0>), dim3(grid), dim3(threads), 0, st, k, fa, A, B);
     return hipGetLastError();
 }
 

@@ -185,6 +185,13 @@ def config3(**kw):
     return sphere_case(mach=0.5, reynolds=300.0, T_wall_ratio=1.5, **kw)
 
 
+def precision_case(nx=512, ny=256, nz=256, center=None):
+    """The precision study as run: the 512 x 256 x 256 sphere (D = 32) with an isothermal wall at
+    T_w = 1.2 T_inf, Ma 0.2, Re 300 (the recipe's Ma 0.5 / T_w = 1.5 T_inf diverges within 50
+    steps from the impulsive start in this scheme, on the oracle as on the GPU)."""
+    return sphere_case(nx=nx, ny=ny, nz=nz, center=center, mach=0.2, reynolds=300.0, T_wall_ratio=1.2)
+
+
 def conduction_number(case):
     """kappa = lambda / (rho C_v) in lattice units: the explicit conduction update of the energy
     equation needs kappa well below 1/(2D)."""
