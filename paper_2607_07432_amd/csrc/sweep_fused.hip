@@ -102,55 +102,91 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     auto s3 = [](int q) { return (q + 6) % 3; };
     auto s2 = [](int q) { return (q + 6) % 2; };
 
-    // ---- (a) predicted macros of plane q on the tile + 2 halo. The global loads are split
-    // from the arithmetic so that they can be issued one stage ahead (prefetch).
-    constexpr int KA = (G::N2 + G::T - 1) / G::T;
-    S pa_f[KA][L::Q];
-    S pa_e[KA];
-    int pa_r[KA];
-    auto load_macros = [&](int q) {
-#pragma unroll
-        for (int kk = 0; kk < KA; ++kk) {
-            const int k = t + kk * G::T;
-            if (k >= G::N2) break;
-            const int jx = k % G::W2, jy = k / G::W2;
-            const long long n = gnode(x0 - 2 + jx, y0 - 2 * G::OY + jy, q);
-#pragma unroll
-            for (int i = 0; i < L::Q; ++i) pa_f[kk][i] = A.f[i * N + n];
-            pa_e[kk] = A.e[n];
-            pa_r[kk] = a.rows.rowmap[n];
+    // ---- Loads. Every node of the tile + 1 halo (R1, one per thread) is read once per plane: its
+    // populations, energy, history and row serve first the macros (stage a) and one plane later
+    // its collision (stage b), so they are kept in registers across one iteration (cur: plane of
+    // the next collision, nxt: plane of the next macros). The outer ring of the tile + 2 halo
+    // (R2 minus R1) only needs macros; threads t < NRING load one ring node each.
+    struct Own {
+        S f[L::Q];
+        S e;
+        S h[2];
+        int r;
+    };
+    constexpr int NRING = D == 3 ? 2 * G::W2 + 2 * (G::H2 - 2) : 2;
+    static_assert(NRING <= G::T, "ring larger than the workgroup");
+    const int jx1 = t % G::W1, jy1 = D == 3 ? t / G::W1 : 0;
+    const int k2own = (jx1 + 1) + G::W2 * (jy1 + G::OY);                        // R2 coords of the own node
+    const bool ring = t < NRING;
+    int rjx, rjy;                                                               // R2 coords of the ring node
+    if (D == 3) {
+        if (t < G::W2) {
+            rjx = t;
+            rjy = 0;
+        } else if (t < 2 * G::W2) {
+            rjx = t - G::W2;
+            rjy = G::H2 - 1;
+        } else {
+            const int k = t - 2 * G::W2;
+            rjx = (k & 1) ? G::W2 - 1 : 0;
+            rjy = 1 + k / 2;
         }
+    } else {
+        rjx = t == 0 ? 0 : G::W2 - 1;
+        rjy = 0;
+    }
+    const int k2ring = rjx + G::W2 * rjy;
+    Own cur, nxt;
+    S rf[L::Q];
+    S re = S(0);
+    int rr = -1;
+    auto load_plane = [&](int q) {
+        const long long n = gnode(x0 - 1 + jx1, y0 - G::OY + jy1, q);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) nxt.f[i] = A.f[i * N + n];
+        nxt.e = A.e[n];
+        nxt.h[0] = A.h2[n];
+        nxt.h[1] = D == 3 ? A.h2[N + n] : S(0);
+        nxt.r = a.rows.rowmap[n];
+        if (ring) {
+            const long long m = gnode(x0 - 2 + rjx, y0 - 2 * G::OY + rjy, q);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) rf[i] = A.f[i * N + m];
+            re = A.e[m];
+            rr = a.rows.rowmap[m];
+        }
+    };
+    auto shift_planes = [&]() { cur = nxt; };
+
+    // ---- (a) predicted macros (rho, half-force velocity, T) of one node into the ring slot sl.
+    auto write_macros = [&](const S* f, S e, int r, int k, int sl) {
+        C drho = 0, j[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const C fv = C(f[i]);
+            drho += fv;
+#pragma unroll
+            for (int b = 0; b < D; ++b)
+                if (L::c[i][b]) j[b] += C(L::c[i][b]) * fv;
+        }
+        const C rho = C(1) + drho;
+        const C ir = C(1) / rho;
+        C uu = 0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) uu += (j[b] * ir) * (j[b] * ir);
+        const C T = ((C(e) + a.e_ref) * ir - C(0.5) * uu) * a.gas.inv_Cv;
+        sm.mac[sl][0][k] = rho;
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            const C fib = r >= 0 ? C(a.rows.fib[(long long)b * a.rows.nrows + r]) : C(0);
+            sm.mac[sl][1 + b][k] = (j[b] + C(0.5) * fib) * ir;
+        }
+        sm.mac[sl][1 + D][k] = T;
     };
     auto compute_macros = [&](int q) {
         const int sl = s3(q);
-#pragma unroll
-        for (int kk = 0; kk < KA; ++kk) {
-            const int k = t + kk * G::T;
-            if (k >= G::N2) break;
-            C drho = 0, j[3] = {0, 0, 0};
-#pragma unroll
-            for (int i = 0; i < L::Q; ++i) {
-                const C f = C(pa_f[kk][i]);
-                drho += f;
-#pragma unroll
-                for (int b = 0; b < D; ++b)
-                    if (L::c[i][b]) j[b] += C(L::c[i][b]) * f;
-            }
-            const C rho = C(1) + drho;
-            const C ir = C(1) / rho;
-            C uu = 0;
-#pragma unroll
-            for (int b = 0; b < D; ++b) uu += (j[b] * ir) * (j[b] * ir);
-            const C T = ((C(pa_e[kk]) + a.e_ref) * ir - C(0.5) * uu) * a.gas.inv_Cv;
-            const int r = pa_r[kk];
-            sm.mac[sl][0][k] = rho;
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                const C fib = r >= 0 ? C(a.rows.fib[(long long)b * a.rows.nrows + r]) : C(0);
-                sm.mac[sl][1 + b][k] = (j[b] + C(0.5) * fib) * ir;
-            }
-            sm.mac[sl][1 + D][k] = T;
-        }
+        write_macros(nxt.f, nxt.e, nxt.r, k2own, sl);
+        if (ring) write_macros(rf, re, rr, k2ring, sl);
     };
 
     auto mcell = [&](int sl, int k2) {
@@ -162,19 +198,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         return c;
     };
 
-    // ---- (b) collision of plane q on the tile + 1 halo (one node per thread)
-    S pb_f[L::Q];
-    S pb_h[2];
-    int pb_r;
-    auto load_collide = [&](int q) {
-        const int jx = t % G::W1, jy = t / G::W1;
-        const long long n = gnode(x0 - 1 + jx, y0 - G::OY + jy, q);
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) pb_f[i] = A.f[i * N + n];
-        pb_h[0] = A.h2[n];
-        pb_h[1] = D == 3 ? A.h2[N + n] : S(0);
-        pb_r = a.rows.rowmap[n];
-    };
+    // ---- (b) collision of plane q on the tile + 1 halo (one node per thread, from cur)
     auto compute_collide = [&](int q) {
         const int sl = s3(q), slm = s3(q - 1), slp = s3(q + 1);
         const int sa = s3(q), sb = s2(q);
@@ -186,7 +210,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
             const long long n = gnode(xu, yu, q);
             C fd[L::Q];
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) fd[i] = C(pb_f[i]);
+            for (int i = 0; i < L::Q; ++i) fd[i] = C(cur.f[i]);
             const Cell<L, C> c0 = mcell(sl, k2);
             Node<L, C> nd;
             nd.rho = c0.rho;
@@ -221,14 +245,14 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
                 st.dmu3[b] = C(0.5) * (cp.rho * cp.u[b] * cp.u[b] * cp.u[b] - cmn.rho * cmn.u[b] * cmn.u[b] * cmn.u[b]);
             }
             C H2[3][3];
-            H2[0][0] = C(pb_h[0]);
+            H2[0][0] = C(cur.h[0]);
             if (D == 3) {
-                H2[1][1] = C(pb_h[1]);
+                H2[1][1] = C(cur.h[1]);
                 H2[2][2] = -(H2[0][0] + H2[1][1]);
             } else {
                 H2[1][1] = -H2[0][0];
             }
-            const int r = pb_r;
+            const int r = cur.r;
             const int nr = a.rows.nrows;
             C fib[3] = {0, 0, 0}, off[3] = {0, 0, 0};
             if (r >= 0) {
@@ -336,35 +360,34 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     };
 
     // Node of this thread in the tile + 1 halo (R1 coords); interior threads own an output node.
-    const int jx1 = t % G::W1, jy1 = D == 3 ? t / G::W1 : 0;
     const bool own_out = jx1 >= 1 && jx1 <= TX && (D == 2 || (jy1 >= 1 && jy1 <= TY));
     const bool own_fx = jx1 <= TX && (D == 2 || (jy1 >= 1 && jy1 <= TY));      // face base + e_x/2
     const bool own_fy = D == 3 && jx1 >= 1 && jx1 <= TX && jy1 <= TY;          // face base + e_y/2
     const int bx1 = jx1, by1 = jy1;
-    const int k2own = (jx1 + 1) + G::W2 * (jy1 + G::OY);                        // R2 coords
     const int xo = x0 - 1 + jx1, yo = y0 - G::OY + jy1;
     const bool real = own_out && xo < g.nx && (D == 2 || yo < g.ny);
     const int frow = D == 3 ? jy1 - 1 : 0;
 
-    // ---- prologue: macros of z0-2 .. z0, collision of z0-1, macros of z0+1, collision of z0
-    load_macros(z0 - 2);
+    // ---- prologue: macros of z0-2 .. z0+1, collisions of z0-1 and z0
+    load_plane(z0 - 2);
     compute_macros(z0 - 2);
-    load_macros(z0 - 1);
+    load_plane(z0 - 1);
     compute_macros(z0 - 1);
-    load_macros(z0);
+    shift_planes();                                 // cur: plane z0 - 1
+    load_plane(z0);
     compute_macros(z0);
     __syncthreads();
-    load_collide(z0 - 1);
     compute_collide(z0 - 1);
+    shift_planes();                                 // cur: plane z0
     __syncthreads();
     Cell<L, C> cm2 = mcell(s3(z0 - 2), k2own);
     Cell<L, C> prev = mcell(s3(z0 - 1), k2own);   // own column, plane p - 1
     __syncthreads();
-    load_macros(z0 + 1);
+    load_plane(z0 + 1);
     compute_macros(z0 + 1);
     __syncthreads();
-    load_collide(z0);
     compute_collide(z0);
+    shift_planes();                                 // cur: plane z0 + 1
     __syncthreads();
     C fm_prev = 0;                                  // energy flux through the p - 1/2 face
     if (own_out) {
@@ -373,8 +396,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         Cell<L, C> c4[4] = {cm2, prev, mcell(s3(z0), k2own), mcell(s3(z0 + 1), k2own)};
         fm_prev = energy_flux<L, C>(a.gas, G::MA, c4, Fr, Fm);
     }
-    load_macros(z0 + 2);
-    load_collide(z0 + 1);
+    load_plane(z0 + 2);                             // nxt: plane z0 + 2
 
     for (int p = z0; p < z1; ++p) {
         compute_macros(p + 2);
@@ -382,10 +404,8 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         compute_collide(p + 1);
         __syncthreads();
         // Issue the next plane's global loads now; they complete while plane p is output.
-        if (p + 1 < z1) {
-            load_macros(p + 3);
-            load_collide(p + 2);
-        }
+        shift_planes();                             // cur: plane p + 2
+        if (p + 1 < z1) load_plane(p + 3);
 
         // ---- (c) output plane p
         C fnew[L::Q];
