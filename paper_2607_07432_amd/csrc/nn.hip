@@ -113,88 +113,113 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
         }
 }
 
-// Weight gradient, split over pixels: part[s][co][k] = sum_{p in split s} dY[p][co] X^[k][p].
-// GEMM with M = co, N = k, and the pixels as the reduction dimension: lane l holds dY at 8
-// consecutive pixels (one image row, since W % 8 == 0) for co = l % 16, and X^ at the same
-// pixels for k = l % 16. dY and X have pixel strides dystride and xstride.
-// Requires cout % (16 TM) == 0, P % 8 == 0, W % 8 == 0, split length % 32 == 0.
-template <int TM, int TN>
-__global__ void __launch_bounds__(256) k_conv_wgrad(const __bf16* __restrict__ dY, int cout, int dystride,
-                                                    const __bf16* __restrict__ X, int cin, int xstride, int taps, int H,
-                                                    int Wd, long long P, int split_len, int nsplit,
-                                                    float* __restrict__ part) {
-    const int lane = threadIdx.x % WAVE;
-    const long long wave = (long long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+// Weight and bias gradients staged through LDS. A workgroup of 4 wavefronts owns a BM x BN tile of
+// (output channel) x (k = tap cin + ci) and a range of pixels (one split). Per step of 32 pixels
+// it reads dY [32 pixels][BM channels] and X^ [32 pixels][BN columns] as 16-byte vectors of 8
+// channels, stores both transposed in LDS ([channel][pixel]) and runs one 16x16x32 MFMA per
+// 16 x 16 sub-tile: lane l reads 8 consecutive pixels of row l % 16. Each wavefront owns 32 x 32.
+// The workgroups of the first k tile also sum dY over their pixels (the bias gradient).
+// Requires cout % BM == 0, cin % 8 == 0 and strides % 8 == 0.
+template <int BM>
+__global__ void __launch_bounds__(256) k_conv_wgrad_lds(const __bf16* __restrict__ dY, int cout, int dys,
+                                                        const __bf16* __restrict__ X, int cin, int xs, int taps, int H,
+                                                        int Wd, long long P, int split_len, int nsplit,
+                                                        float* __restrict__ part, float* __restrict__ bpart) {
+    constexpr int BN = 4096 / BM;
+    constexpr int KP = 32, LD = KP + 8;
+    __shared__ __bf16 As[BM][LD];
+    __shared__ __bf16 Bs[BN][LD];
+    __shared__ float bred[256 / (BM / 8)][BM];
     const int K = taps * cin;
-    const int co_tiles = cout / (16 * TM), k_tiles = (K + 16 * TN - 1) / (16 * TN);
-    const long long tiles = (long long)co_tiles * k_tiles * nsplit;
-    if (wave >= tiles) return;
-    const int cot = (int)(wave % co_tiles);
-    const int kt = (int)((wave / co_tiles) % k_tiles);
-    const int s = (int)(wave / ((long long)co_tiles * k_tiles));
-    const int co0 = cot * 16 * TM, k0 = kt * 16 * TN;
+    const int co_tiles = cout / BM, k_tiles = (K + BN - 1) / BN;
+    const int b = blockIdx.x;
+    const int cot = b % co_tiles, kt = (b / co_tiles) % k_tiles, s = b / (co_tiles * k_tiles);
+    if (s >= nsplit) return;
+    const int co0 = cot * BM, k0 = kt * BN;
+    const int t = threadIdx.x, lane = t % WAVE, wv = t / WAVE;
+    constexpr int WN = BN / 32;                    // wavefronts along k
+    const int wm = wv / WN, wn = wv % WN;
     const int HW = H * Wd;
-    int tap[TN], ci[TN];
-    bool kv[TN];
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-        const int k = k0 + j * 16 + lane % 16;
-        kv[j] = k < K;
-        tap[j] = kv[j] ? k / cin : 0;
-        ci[j] = kv[j] ? k - tap[j] * cin : 0;
-    }
-    f32x4 acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const long long pbeg = (long long)s * split_len;
     const long long pend = pbeg + split_len < P ? pbeg + split_len : P;
-    const __bf16 z = (__bf16)0.f;
-    for (long long q = pbeg; q < pend; q += 32) {
-        const long long p = q + (lane / 16) * 8;     // first of this lane's 8 pixels (same image row)
-        const bool pv = p < pend;
-        const long long n = p / HW;
-        const int r = (int)(p - n * HW);
-        const int y = r / Wd, x = r - (r / Wd) * Wd;
-        bf16x8 a[TM], b[TN];
+    // staging roles
+    constexpr int AG = BM / 8;                     // 8-channel groups of dY per pixel
+    const int a_pix = t / AG, a_g = t % AG;        // valid for t < 32 * AG
+    const bool a_on = t < KP * AG;
+    float bsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    f32x4 acc[2][2];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            const __bf16* src = dY + p * dystride + co0 + i * 16 + lane % 16;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) a[i][e] = pv ? src[(long long)e * dystride] : z;
-        }
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const int dy = taps == 9 ? tap[j] / 3 - 1 : 0;
-            const int dx = taps == 9 ? tap[j] % 3 - 1 : 0;
-            const int yy = y + dy;
-            const bool rowin = pv && kv[j] && yy >= 0 && yy < H;
-            const __bf16* src = X + (n * HW + (long long)yy * Wd) * xstride + ci[j];
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = {};
+    for (long long q = pbeg; q < pend; q += KP) {
+        if (a_on) {
+            const long long p = q + a_pix;
+            const bf16x8 v = p < pend ? *reinterpret_cast<const bf16x8*>(dY + p * dys + co0 + 8 * a_g) : zero;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int xx = x + e + dx;
-                b[j][e] = (rowin && xx >= 0 && xx < Wd) ? src[(long long)xx * xstride] : z;
+                As[8 * a_g + e][a_pix] = v[e];
+                bsum[e] += (float)v[e];
             }
         }
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int r = 0; r < (BN * KP / 8 + 255) / 256; ++r) {
+            const int v_ = t + 256 * r;
+            if (v_ < BN * KP / 8) {
+                const int pix = v_ / (BN / 8), g = v_ % (BN / 8);
+                const int k = k0 + 8 * g;
+                const long long p = q + pix;
+                bf16x8 v = zero;
+                if (k < K && p < pend) {
+                    const int tap = k / cin, ci = k - tap * cin;
+                    const int dy = taps == 9 ? tap / 3 - 1 : 0, dx = taps == 9 ? tap % 3 - 1 : 0;
+                    const long long n = p / HW;
+                    const int rr = (int)(p - n * HW);
+                    const int y = rr / Wd + dy, x = rr % Wd + dx;
+                    if (y >= 0 && y < H && x >= 0 && x < Wd)
+                        v = *reinterpret_cast<const bf16x8*>(X + (n * HW + (long long)y * Wd + x) * xs + ci);
+                }
 #pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int e = 0; e < 8; ++e) Bs[8 * g + e][pix] = v[e];
+            }
+        }
+        __syncthreads();
+        bf16x8 a[2], bb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + i * 16 + lane % 16][8 * (lane / 16)]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bb[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + j * 16 + lane % 16][8 * (lane / 16)]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
     }
     float* out = part + (long long)s * cout * K;
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            if (!kv[j]) continue;
+        for (int j = 0; j < 2; ++j) {
+            const int k = k0 + wn * 32 + j * 16 + lane % 16;
+            if (k >= K) continue;
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int co = co0 + i * 16 + (lane / 16) * 4 + rr;
-                const int k = k0 + j * 16 + lane % 16;
-                out[(long long)co * K + k] = acc[i][j][rr];
+            for (int r = 0; r < 4; ++r) {
+                const int co = co0 + wm * 32 + i * 16 + (lane / 16) * 4 + r;
+                out[(long long)co * K + k] = acc[i][j][r];
             }
         }
+    if (kt == 0) {
+        if (a_on)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bred[a_pix][8 * a_g + e] = bsum[e];
+        __syncthreads();
+        if (t < BM) {
+            float v = 0.f;
+            for (int r = 0; r < KP; ++r) v += bred[r][t];
+            bpart[(long long)s * cout + co0 + t] = v;
+        }
+    }
 }
 
 // Fixed-order sum of the split partials into the FP32 gradient.
@@ -204,23 +229,6 @@ __global__ void k_sum_splits(const float* __restrict__ part, int nsplit, long lo
     float s = 0.f;
     for (int k = 0; k < nsplit; ++k) s += part[(long long)k * n + i];
     g[i] = s;
-}
-
-// Bias gradient: db[c] = sum_p dY[p][c], block partials over pixel ranges, then a fixed-order sum.
-constexpr int BG_PIX = 2048;
-__global__ void __launch_bounds__(256) k_bias_part(const __bf16* __restrict__ dY, int c, int stride, long long P,
-                                                   float* __restrict__ part) {
-    const long long p0 = (long long)blockIdx.y * BG_PIX;
-    const int ch = blockIdx.x * 64 + threadIdx.x % 64;
-    const int row = threadIdx.x / 64;
-    __shared__ float red[4][64];
-    float s = 0.f;
-    if (ch < c)
-        for (long long p = p0 + row; p < p0 + BG_PIX && p < P; p += 4) s += (float)dY[p * stride + ch];
-    red[row][threadIdx.x % 64] = s;
-    __syncthreads();
-    if (row == 0 && ch < c)
-        part[(long long)blockIdx.y * c + ch] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
 // W'[ci][8 - t][co] = W[co][t][ci]: backward data is the forward convolution of dY with W'.
@@ -595,8 +603,7 @@ size_t layout(nn_unet* u, int B, int H, int W, char* base) {
     // split partials: at most 64 splits of the largest weight
     const size_t split_floats = (size_t)64 * maxw;
     float* split = (float*)take(split_floats * 4);
-    const size_t small_floats = (size_t)std::max<long long>((P0 + HEAD_PIX - 1) / HEAD_PIX * HEAD_NP,
-                                                            (P0 + BG_PIX - 1) / BG_PIX * 256);
+    const size_t small_floats = (size_t)std::max<long long>((P0 + HEAD_PIX - 1) / HEAD_PIX * HEAD_NP, 256 * 256);
     float* small = (float*)take(small_floats * 4);
     double* lossp = (double*)take(((P0 + LOSS_PIX - 1) / LOSS_PIX) * 2 * 8);
     double* loss = (double*)take(2 * 8);
@@ -678,24 +685,30 @@ hipError_t conv_wgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, co
                       int W) {
     const long long P = (long long)B * H * W;
     const int K = ly.taps * ly.cin;
-    constexpr int TM = 2, TN = 2;
-    if (ly.cout % (16 * TM) || W % 8 || P % 8) return hipErrorInvalidValue;
+    const int BM = ly.cout % 64 == 0 ? 64 : 32;
+    const int BN = 4096 / BM;
+    if (ly.cout % BM || ly.cin % 8 || dys % 8 || xs % 8) return hipErrorInvalidValue;
     const long long wsz = (long long)ly.cout * K;
-    int nsplit = (int)std::min<long long>(64, std::max<long long>(1, P / 4096));
+    const long long tiles = (long long)(ly.cout / BM) * ((K + BN - 1) / BN);
+    // splits: enough workgroups to fill the chip, at least 256 pixels each, within the partial buffer
+    long long nsplit = std::max<long long>(1, std::min<long long>(P / 256, (2048 + tiles - 1) / tiles));
+    nsplit = std::min<long long>(nsplit, 256);
     while ((size_t)nsplit * wsz > u->split_floats && nsplit > 1) --nsplit;
+    while ((size_t)nsplit * ly.cout > u->small_floats && nsplit > 1) --nsplit;
     long long split_len = (P + nsplit - 1) / nsplit;
     split_len = (split_len + 31) / 32 * 32;
-    nsplit = (int)((P + split_len - 1) / split_len);
-    const long long tiles = (long long)(ly.cout / (16 * TM)) * ((K + 16 * TN - 1) / (16 * TN)) * nsplit;
-    hipLaunchKernelGGL((k_conv_wgrad<TM, TN>), dim3(blocks(tiles, 4)), dim3(256), 0, u->stream, dY, ly.cout, dys, X,
-                       ly.cin, xs, ly.taps, H, W, P, (int)split_len, nsplit, u->split);
-    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(wsz)), dim3(256), 0, u->stream, (const float*)u->split, nsplit, wsz,
+    nsplit = (P + split_len - 1) / split_len;
+    const dim3 grid((unsigned)(tiles * nsplit));
+    if (BM == 64)
+        hipLaunchKernelGGL(k_conv_wgrad_lds<64>, grid, dim3(256), 0, u->stream, dY, ly.cout, dys, X, ly.cin, xs, ly.taps,
+                           H, W, P, (int)split_len, (int)nsplit, u->split, u->small);
+    else
+        hipLaunchKernelGGL(k_conv_wgrad_lds<32>, grid, dim3(256), 0, u->stream, dY, ly.cout, dys, X, ly.cin, xs, ly.taps,
+                           H, W, P, (int)split_len, (int)nsplit, u->split, u->small);
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(wsz)), dim3(256), 0, u->stream, (const float*)u->split, (int)nsplit, wsz,
                        u->grad + ly.w_off);
-    const int nb = (int)((P + BG_PIX - 1) / BG_PIX);
-    hipLaunchKernelGGL(k_bias_part, dim3((ly.cout + 63) / 64, nb), dim3(256), 0, u->stream, dY, ly.cout, dys, P,
-                       u->small);
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(ly.cout)), dim3(256), 0, u->stream, (const float*)u->small, nb, ly.cout,
-                       u->grad + ly.b_off);
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(ly.cout)), dim3(256), 0, u->stream, (const float*)u->small, (int)nsplit,
+                       ly.cout, u->grad + ly.b_off);
     return hipGetLastError();
 }
 
