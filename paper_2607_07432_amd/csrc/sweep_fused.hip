@@ -387,6 +387,10 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     compute_macros(z0 + 1);
     __syncthreads();
     compute_collide(z0);
+    // energy and row of the own node for its output one plane later (its forcing is prefetched)
+    S ekeep = cur.e;
+    int rkeep = cur.r;
+    C fEkeep = rkeep >= 0 ? C(a.rows.fE[rkeep]) : C(0);
     shift_planes();                                 // cur: plane z0 + 1
     __syncthreads();
     C fm_prev = 0;                                  // energy flux through the p - 1/2 face
@@ -404,6 +408,11 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         compute_collide(p + 1);
         __syncthreads();
         // Issue the next plane's global loads now; they complete while plane p is output.
+        const S eout = ekeep;                       // own node, plane p
+        const C fEout = fEkeep;
+        ekeep = cur.e;                              // plane p + 1
+        rkeep = cur.r;
+        fEkeep = rkeep >= 0 ? C(a.rows.fE[rkeep]) : C(0);
         shift_planes();                             // cur: plane p + 2
         if (p + 1 < z1) load_plane(p + 3);
 
@@ -443,9 +452,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
             }
             if (xo >= g.nx - 2) continue;
         }
-        const int r = a.rows.rowmap[n];
-        const C fE = r >= 0 ? C(a.rows.fE[r]) : C(0);
-        const C enew = C(A.e[n]) - ediv + fE;
+        const C enew = C(eout) - ediv + fEout;
         const int copies = (g.bc_x == 1 && xo == g.nx - 3) ? 3 : 1;
         for (int c = 0; c < copies; ++c) {
 #pragma unroll
