@@ -3,16 +3,19 @@
 // (11), (A.3)-(A.16)); every node update reads and writes the state once.
 //
 // A workgroup owns a TX x TY tile of the plane normal to the marching axis (z in 3D,
-// y in 2D) and marches along that axis over a chunk of planes. Three rings live in LDS:
-//   mac  : predicted macros (rho, half-force velocity, T) of 3 planes on the tile + 2 halo;
+// y in 2D) and marches along that axis over a chunk of planes. Rings in LDS:
+//   mac  : predicted macros (rho, half-force velocity, T) of 4 planes on the tile + 2 halo;
 //   fcA  : post-collision populations moving +1 along the marching axis, 3 planes, tile + 1;
-//   fcB  : the other post-collision populations, 2 planes, tile + 1.
-// Per output plane p: (a) macros of plane p+2, (b) collision of plane p+1 (needs macros of
-// p..p+2 for the velocity gradients), (c) output of plane p: pull streaming from planes
-// p-1..p+1, face fluxes of the +x/+y faces (shared through LDS) and of the p+1/2 face
-// (the p-1/2 face is carried in a register from the previous plane).
-// Only the in-plane halo is recomputed; along the marching axis each plane is computed
-// once per chunk (plus a 2-plane warm-up).
+//   fcB  : the other post-collision populations, 2 planes, tile + 1;
+//   fex/fey : in-plane face fluxes of the last two output planes.
+// Per iteration p: (a) macros of plane p+2; barrier; (b) collision of plane p+1 (needs macros
+// of p..p+2 for the velocity gradients) and the end of the output of plane p-1 (flux
+// divergence, energy update, stores); barrier; (c) the first part of the output of plane p:
+// pull streaming from planes p-1..p+1 into registers, face fluxes of the +x/+y faces (into the
+// flux buffer) and of the p+1/2 face (the p-1/2 face is carried in a register).
+// Each node of the tile + 1 halo is loaded once per plane, one iteration ahead, and kept in
+// registers from its macros to its collision. Only the in-plane halo is recomputed; along the
+// marching axis each plane is computed once per chunk (plus a 2-plane warm-up).
 #include "kernels.hpp"
 
 namespace lbmib {
@@ -62,11 +65,11 @@ struct FG {
 template <class L, class S, class C, int TX, int TY>
 struct FusedSmem {
     using G = FG<L, TX, TY>;
-    C mac[3][G::NM][G::N2];
+    C mac[4][G::NM][G::N2];
     C fcA[3][G::NA][G::N1];
     C fcB[2][G::NB][G::N1];
-    C fex[TY][TX + 1];
-    C fey[G::D == 3 ? TY + 1 : 1][TX];
+    C fex[2][TY][TX + 1];
+    C fey[2][G::D == 3 ? TY + 1 : 1][TX];
 };
 
 struct FusedArgs {
@@ -99,8 +102,9 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         if (D == 3) return (long long)xw + (long long)g.nx * ((long long)wr(y, g.ny) + (long long)g.ny * wr(m, nm));
         return (long long)xw + (long long)g.nx * wr(m, nm);
     };
-    auto s3 = [](int q) { return (q + 6) % 3; };
-    auto s2 = [](int q) { return (q + 6) % 2; };
+    auto s4 = [](int q) { return (q + 8) % 4; };  // macros ring
+    auto s3 = [](int q) { return (q + 6) % 3; };  // post-collision +z movers
+    auto s2 = [](int q) { return (q + 6) % 2; };  // other post-collision populations, flux buffers
 
     // ---- Loads. Every node of the tile + 1 halo (R1, one per thread) is read once per plane: its
     // populations, energy, history and row serve first the macros (stage a) and one plane later
@@ -184,7 +188,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         sm.mac[sl][1 + D][k] = T;
     };
     auto compute_macros = [&](int q) {
-        const int sl = s3(q);
+        const int sl = s4(q);
         write_macros(nxt.f, nxt.e, nxt.r, k2own, sl);
         if (ring) write_macros(rf, re, rr, k2ring, sl);
     };
@@ -200,7 +204,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
 
     // ---- (b) collision of plane q on the tile + 1 halo (one node per thread, from cur)
     auto compute_collide = [&](int q) {
-        const int sl = s3(q), slm = s3(q - 1), slp = s3(q + 1);
+        const int sl = s4(q), slm = s4(q - 1), slp = s4(q + 1);
         const int sa = s3(q), sb = s2(q);
         {
             const int k = t;
@@ -350,7 +354,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     auto inplane_flux = [&](int ax, int bx, int by, int q) -> C {
         C Fr, Fm[3];
         lb_flux(ax, bx, by, q, Fr, Fm);
-        const int sl = s3(q);
+        const int sl = s4(q);
         const int k2 = (bx + 1) + G::W2 * (by + G::OY);
         const int stride = ax == 0 ? 1 : G::W2;
         Cell<L, C> c4[4];
@@ -380,8 +384,8 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     compute_collide(z0 - 1);
     shift_planes();                                 // cur: plane z0
     __syncthreads();
-    Cell<L, C> cm2 = mcell(s3(z0 - 2), k2own);
-    Cell<L, C> prev = mcell(s3(z0 - 1), k2own);   // own column, plane p - 1
+    Cell<L, C> cm2 = mcell(s4(z0 - 2), k2own);
+    Cell<L, C> prev = mcell(s4(z0 - 1), k2own);   // own column, plane p - 1
     __syncthreads();
     load_plane(z0 + 1);
     compute_macros(z0 + 1);
@@ -397,17 +401,49 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     if (own_out) {
         C Fr, Fm[3];
         lb_flux(G::MA, bx1, by1, z0 - 1, Fr, Fm);
-        Cell<L, C> c4[4] = {cm2, prev, mcell(s3(z0), k2own), mcell(s3(z0 + 1), k2own)};
+        Cell<L, C> c4[4] = {cm2, prev, mcell(s4(z0), k2own), mcell(s4(z0 + 1), k2own)};
         fm_prev = energy_flux<L, C>(a.gas, G::MA, c4, Fr, Fm);
     }
     load_plane(z0 + 2);                             // nxt: plane z0 + 2
+
+    // The output of plane p is prepared after the second barrier of iteration p (streaming into
+    // registers, face fluxes into the buffer p % 2) and finished after the first barrier of
+    // iteration p + 1 (flux divergence, energy update, stores), so each plane needs two barriers.
+    C pf[L::Q];                                     // streamed populations of the pending plane
+    C pfm = 0, pfmp = 0;                            // its p + 1/2 and p - 1/2 face fluxes
+    S pe = S(0);
+    C pfE = 0;
+    auto finish = [&](int q) {
+        if (!real) return;
+        const int fb = s2(q);
+        C ediv = (sm.fex[fb][frow][jx1] - sm.fex[fb][frow][jx1 - 1]) + (pfm - pfmp);
+        if (D == 3) ediv += sm.fey[fb][jy1][jx1 - 1] - sm.fey[fb][jy1 - 1][jx1 - 1];
+        const long long n = gnode(xo, yo, q);
+        if (g.bc_x == 1) {
+            if (xo < 2) {
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i) B.f[i * N + n] = S(a.fdev[i]);
+                B.e[n] = S(0);
+                return;
+            }
+            if (xo >= g.nx - 2) return;
+        }
+        const C enew = C(pe) - ediv + pfE;
+        const int copies = (g.bc_x == 1 && xo == g.nx - 3) ? 3 : 1;
+        for (int c = 0; c < copies; ++c) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) B.f[i * N + n + c] = S(pf[i]);
+            B.e[n + c] = S(enew);
+        }
+    };
 
     for (int p = z0; p < z1; ++p) {
         compute_macros(p + 2);
         __syncthreads();
         compute_collide(p + 1);
+        if (p > z0) finish(p - 1);
         __syncthreads();
-        // Issue the next plane's global loads now; they complete while plane p is output.
+        // Issue the next plane's global loads now; they complete while plane p is prepared.
         const S eout = ekeep;                       // own node, plane p
         const C fEout = fEkeep;
         ekeep = cur.e;                              // plane p + 1
@@ -416,50 +452,32 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         shift_planes();                             // cur: plane p + 2
         if (p + 1 < z1) load_plane(p + 3);
 
-        // ---- (c) output plane p
-        C fnew[L::Q];
+        // ---- (c) output plane p, first part
+        const int fb = s2(p);
         if (own_out) {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
-                fnew[i] = fcr(i, bx1 - L::c[i][0], by1 - (D == 3 ? L::c[i][1] : 0), p - cm<L>(i));
+                pf[i] = fcr(i, bx1 - L::c[i][0], by1 - (D == 3 ? L::c[i][1] : 0), p - cm<L>(i));
         }
-        if (own_fx) sm.fex[frow][jx1] = inplane_flux(0, bx1, by1, p);
-        if (D == 3 && own_fy) sm.fey[jy1][jx1 - 1] = inplane_flux(1, bx1, by1, p);
+        if (own_fx) sm.fex[fb][frow][jx1] = inplane_flux(0, bx1, by1, p);
+        if (D == 3 && own_fy) sm.fey[fb][jy1][jx1 - 1] = inplane_flux(1, bx1, by1, p);
         C fm_now = 0;
         if (own_out) {
             C Fr, Fm[3];
             lb_flux(G::MA, bx1, by1, p, Fr, Fm);
-            const Cell<L, C> cp0 = mcell(s3(p), k2own);
-            Cell<L, C> c4[4] = {prev, cp0, mcell(s3(p + 1), k2own), mcell(s3(p + 2), k2own)};
+            const Cell<L, C> cp0 = mcell(s4(p), k2own);
+            Cell<L, C> c4[4] = {prev, cp0, mcell(s4(p + 1), k2own), mcell(s4(p + 2), k2own)};
             fm_now = energy_flux<L, C>(a.gas, G::MA, c4, Fr, Fm);
             prev = cp0;
         }
-        __syncthreads();
-        C ediv = 0;
-        if (own_out) {
-            ediv = (sm.fex[frow][jx1] - sm.fex[frow][jx1 - 1]) + (fm_now - fm_prev);
-            if (D == 3) ediv += sm.fey[jy1][jx1 - 1] - sm.fey[jy1 - 1][jx1 - 1];
-        }
+        pfm = fm_now;
+        pfmp = fm_prev;
+        pe = eout;
+        pfE = fEout;
         fm_prev = fm_now;
-        if (!real) continue;
-        const long long n = gnode(xo, yo, p);
-        if (g.bc_x == 1) {
-            if (xo < 2) {
-#pragma unroll
-                for (int i = 0; i < L::Q; ++i) B.f[i * N + n] = S(a.fdev[i]);
-                B.e[n] = S(0);
-                continue;
-            }
-            if (xo >= g.nx - 2) continue;
-        }
-        const C enew = C(eout) - ediv + fEout;
-        const int copies = (g.bc_x == 1 && xo == g.nx - 3) ? 3 : 1;
-        for (int c = 0; c < copies; ++c) {
-#pragma unroll
-            for (int i = 0; i < L::Q; ++i) B.f[i * N + n + c] = S(fnew[i]);
-            B.e[n + c] = S(enew);
-        }
     }
+    __syncthreads();
+    finish(z1 - 1);
 }
 
 template <class L, class S, class C, int TX, int TY, int SM>
