@@ -196,7 +196,7 @@ def main():
     ap.add_argument('--workload', choices=('sphere3d', 'batch64', 'learned'), default='sphere3d')
     ap.add_argument('--train-cases', type=int, default=2000)
     ap.add_argument('--heldout-cases', type=int, default=512)
-    ap.add_argument('--epochs', type=int, default=40)
+    ap.add_argument('--epochs', type=int, default=80)
     args = ap.parse_args()
 
     if args.gpus != 1:
