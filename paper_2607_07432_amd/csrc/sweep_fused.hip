@@ -69,7 +69,7 @@ struct FusedSmem {
     C fcA[3][G::NA][G::N1];
     C fcB[2][G::NB][G::N1];
     C fex[2][TY][TX + 1];
-    C fey[2][G::D == 3 ? TY + 1 : 1][TX];
+    C fey[2][G::D == 3 ? TY + 1 : 1][G::D == 3 ? TX : 1];   // unused in 2D
 };
 
 struct FusedArgs {
@@ -417,7 +417,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         if (!real) return;
         const int fb = s2(q);
         C ediv = (sm.fex[fb][frow][jx1] - sm.fex[fb][frow][jx1 - 1]) + (pfm - pfmp);
-        if (D == 3) ediv += sm.fey[fb][jy1][jx1 - 1] - sm.fey[fb][jy1 - 1][jx1 - 1];
+        if constexpr (D == 3) ediv += sm.fey[fb][jy1][jx1 - 1] - sm.fey[fb][jy1 - 1][jx1 - 1];
         const long long n = gnode(xo, yo, q);
         if (g.bc_x == 1) {
             if (xo < 2) {
@@ -460,7 +460,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
                 pf[i] = fcr(i, bx1 - L::c[i][0], by1 - (D == 3 ? L::c[i][1] : 0), p - cm<L>(i));
         }
         if (own_fx) sm.fex[fb][frow][jx1] = inplane_flux(0, bx1, by1, p);
-        if (D == 3 && own_fy) sm.fey[fb][jy1][jx1 - 1] = inplane_flux(1, bx1, by1, p);
+        if constexpr (D == 3) if (own_fy) sm.fey[fb][jy1][jx1 - 1] = inplane_flux(1, bx1, by1, p);
         C fm_now = 0;
         if (own_out) {
             C Fr, Fm[3];
