@@ -238,7 +238,6 @@ int lbm_init_grid(const lbm_params* p, void* ws, size_t bytes, void* stream, lbm
     h->N = (long long)p->nx * p->ny * p->nz;
     h->stream = (hipStream_t)stream;
     if (const char* ch = std::getenv("LBMIB_FUSED_CHUNK")) h->chunk = std::atoi(ch);
-    if (const char* tv = std::getenv("LBMIB_FUSED_TILE")) h->variant = std::atoi(tv);
     layout(*p, (char*)ws, &h->d);
 
     SweepArgs& a = h->args;
@@ -386,7 +385,7 @@ int run_steps(lbm_handle* h, int n, hipEvent_t* ev) {
                 if (h->p.sweep == LBM_SWEEP_THREE_PASS)
                     r = launch_split_step<LT, ST, ST>(h->args, A, B, M, fcol, h->stream);
                 else
-                    r = launch_fused_step<LT, ST>(h->args, A, B, h->chunk, h->variant, h->stream);
+                    r = launch_fused_step<LT, ST>(h->args, A, B, h->chunk, h->stream);
             }
             if (r == hipSuccess && e4) r = hipEventRecord(e4[3], h->stream);
             if (r == hipSuccess && last)

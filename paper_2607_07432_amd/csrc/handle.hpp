@@ -46,7 +46,6 @@ struct lbm_handle {
     std::vector<double> host_stage;
     int method = 0;
     int chunk = 0;         // planes per workgroup of the fused sweep (0: per-lattice default)
-    int variant = 0;       // tile variant of the fused sweep (tuning)
     int markers_set = 0;
     int stepped = 0;       // a step has run since the body was set
     int any_step = 0;

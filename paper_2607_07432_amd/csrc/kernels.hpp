@@ -114,7 +114,7 @@ template <class L, class S, class C>
 hipError_t launch_split_step(const SweepArgs& a, StateP<S> A, StateP<S> B, C* M, C* fcol, hipStream_t st);
 
 template <class L, class S>
-hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, int variant, hipStream_t st);
+hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, hipStream_t st);
 
 template <class L, class S>
 hipError_t launch_init_state(const SweepArgs& a, StateP<S> A, hipStream_t st);

@@ -575,14 +575,9 @@ hipError_t launch_fused_tile(const SweepArgs& a, StateP<S> A, StateP<S> B, int c
     return hipGetLastError();
 }
 
-// variant 1 selects the 14 x 14 tile (256 threads, two workgroups per CU) for FP32 D3Q19.
 template <class L, class S>
-hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, int variant,
-                             hipStream_t st) {
+hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, hipStream_t st) {
     using TL = Tile<L, S>;
-    if constexpr (L::D == 3 && sizeof(S) == 4) {
-        if (variant == 1) return launch_fused_tile<L, S, 14, 14>(a, A, B, chunk, 32, st);
-    }
     return launch_fused_tile<L, S, TL::TX, TL::TY>(a, A, B, chunk, TL::CHUNK, st);
 }
 
@@ -622,9 +617,9 @@ template hipError_t launch_fused_batch<D2Q9, double>(const CaseDesc<double>*, in
 template int fused_batch_occupancy<D2Q9, float>(int);
 template int fused_batch_occupancy<D2Q9, double>(int);
 
-template hipError_t launch_fused_step<D2Q9, float>(const SweepArgs&, StateP<float>, StateP<float>, int, int, hipStream_t);
-template hipError_t launch_fused_step<D2Q9, double>(const SweepArgs&, StateP<double>, StateP<double>, int, int, hipStream_t);
-template hipError_t launch_fused_step<D3Q19, float>(const SweepArgs&, StateP<float>, StateP<float>, int, int, hipStream_t);
-template hipError_t launch_fused_step<D3Q19, double>(const SweepArgs&, StateP<double>, StateP<double>, int, int, hipStream_t);
+template hipError_t launch_fused_step<D2Q9, float>(const SweepArgs&, StateP<float>, StateP<float>, int, hipStream_t);
+template hipError_t launch_fused_step<D2Q9, double>(const SweepArgs&, StateP<double>, StateP<double>, int, hipStream_t);
+template hipError_t launch_fused_step<D3Q19, float>(const SweepArgs&, StateP<float>, StateP<float>, int, hipStream_t);
+template hipError_t launch_fused_step<D3Q19, double>(const SweepArgs&, StateP<double>, StateP<double>, int, hipStream_t);
 
 }  // namespace lbmib
