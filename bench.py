@@ -153,7 +153,9 @@ def bench_batch(args):
                    'nodes': N, 'markers': M, 'tuned': cfg, 'parallelism': 'single GPU'},
         'roofline': {'bound': 'hbm', 'kernel': 'persistent batched fused sweep', 'achieved': round(achieved, 1),
                      'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4),
-                     'bytes_per_node': bytes_per_node, 'sweep_ms': round(sweep_ms, 5), 'traffic': None},
+                     'bytes_per_node': bytes_per_node, 'sweep_ms': round(sweep_ms, 5),
+                     'traffic': read_traffic('batch64_d2q9_f32', sweep_sources_hash())
+                     if args.precision == 32 and cfg.get('tile_x') == 254 else None},
         'kernel_ms': {'markers': round(float(kernel_ms[0]), 5), 'spread': round(float(kernel_ms[1]), 5),
                       'sweep': round(sweep_ms, 5)},
         'nonfinite_cases': n_bad,
