@@ -185,6 +185,39 @@ def bench_learned(args):
     print(json.dumps(out))
 
 
+def bench_methods(args):
+    """DIBM vs FODIBM vs FODIBM-R on the same bodies (fixed and turning walls): boundary-condition
+    errors, loads and the per-step cost of each method."""
+    from paper_2607_07432_amd import methods
+    log = lambda msg: print(f'[methods] {msg}', file=sys.stderr, flush=True)
+    res = methods.compare(quick=args.quick, log=log)
+    red_dir = methods.reduction(res, 0, 'eps_dir')
+    sph = res[3]['methods']
+    cost = None
+    if sph['FODIBM-R'].get('finite') and sph['FODIBM'].get('finite'):
+        cost = 100.0 * (sph['FODIBM-R']['step_ms'] - sph['FODIBM']['step_ms']) / sph['FODIBM']['step_ms']
+    out = {
+        'metric': 'change of the mean no-slip error, FODIBM-R vs FODIBM (cylinder, Re 40, isothermal)',
+        'value': None if red_dir is None else round(red_dir, 3), 'unit': '%', 'n_gpus': 1, 'steps': None,
+        'warmup': 0, 'ms_per_step': None, 'higher_is_better': False, 'scaling': 'weak', 'vs_baseline': None,
+        'dtype': 'f64 (2D), f32 (3D)', 'data': 'synthetic',
+        'config': {'workload': 'methods: DIBM / FODIBM / FODIBM-R on a 200x100 cylinder at Ma 0.1 (isothermal, adiabatic, '
+                               'turning) and a 384x192x192 sphere (fixed, turning at omega* 0.3 and 0.6)'},
+        'reconstruction_cost_pct': None if cost is None else round(cost, 3),
+        'changes_pct': {
+            'eps_dir_isothermal_cylinder': red_dir,
+            'eps_iso_isothermal_cylinder': methods.reduction(res, 0, 'eps_iso'),
+            'eps_dir_adiabatic_cylinder': methods.reduction(res, 1, 'eps_dir'),
+            'eps_neu_adiabatic_cylinder': methods.reduction(res, 1, 'eps_neu'),
+            'eps_dir_turning_cylinder': methods.reduction(res, 2, 'eps_dir'),
+            'eps_dir_sphere': methods.reduction(res, 3, 'eps_dir'),
+            'eps_neu_sphere': methods.reduction(res, 3, 'eps_neu'),
+        },
+        'cases': res,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -195,7 +228,8 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--copy-kernel', type=int, default=0)
     ap.add_argument('--sweep', choices=('fused', 'threepass'), default='fused')
-    ap.add_argument('--workload', choices=('sphere3d', 'batch64', 'learned'), default='sphere3d')
+    ap.add_argument('--workload', choices=('sphere3d', 'batch64', 'learned', 'methods'), default='sphere3d')
+    ap.add_argument('--quick', action='store_true', help='methods workload: shorter runs')
     ap.add_argument('--train-cases', type=int, default=2000)
     ap.add_argument('--heldout-cases', type=int, default=512)
     ap.add_argument('--epochs', type=int, default=80)
@@ -213,6 +247,9 @@ def main():
         return
     if args.workload == 'learned':
         bench_learned(args)
+        return
+    if args.workload == 'methods':
+        bench_methods(args)
         return
 
     import torch

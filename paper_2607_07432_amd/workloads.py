@@ -136,21 +136,44 @@ def _markers_common(X, n, t_kind, t_value):
                 t_value=np.full(m, t_value, dtype=np.float64))
 
 
+def rotation_wall_velocity(X, center, omega):
+    """Wall velocity of a body turning at angular velocity omega about the z axis through
+    center: u = omega e_z x (X - c), the first two components in 2D."""
+    X = np.asarray(X, dtype=np.float64)
+    u = np.zeros_like(X)
+    u[:, 0] = -omega * (X[:, 1] - center[1])
+    u[:, 1] = omega * (X[:, 0] - center[0])
+    return u
+
+
 def cylinder_case(nx=200, ny=100, center=(60.0, 50.0), diameter=20.0, markers=63, mach=0.2,
-                  reynolds=40.0, T_wall_ratio=1.2, method=METHOD_FODIBM_R, kernel=KERNEL_COS, steps=1000):
-    """2D cylinder, no-slip, isothermal wall: D2Q9, 200 x 100, D = 20 at (60, 50), 63 markers."""
-    T_inf, T_w = reference_temperatures(T_wall_ratio)
+                  reynolds=40.0, T_wall_ratio=1.2, method=METHOD_FODIBM_R, kernel=KERNEL_COS, steps=1000,
+                  omega_star=0.0):
+    """2D cylinder, no-slip: D2Q9, 200 x 100, D = 20 at (60, 50), 63 markers. Isothermal wall
+    (T_w = T_wall_ratio T_inf) or, with T_wall_ratio None, adiabatic (theta_inf = 1). With
+    omega_star the cylinder turns counter-clockwise at omega = 2 omega_star |u_inf| / D, i.e. its
+    surface moves at omega_star |u_inf|."""
+    if T_wall_ratio is None:
+        T_inf, T_w, kind, tv = 1.0, 1.0, T_NEUMANN, 0.0
+    else:
+        T_inf, T_w = reference_temperatures(T_wall_ratio)
+        kind, tv = T_DIRICHLET, T_w
     u, mu, lam = flow_units(mach, reynolds, diameter, T_inf)
     X, n = cylinder_markers(center, diameter / 2.0, markers)
+    mk = _markers_common(X, n, kind, tv)
+    if omega_star:
+        mk['u_wall'] = rotation_wall_velocity(X, center, 2.0 * omega_star * u / diameter)
     return Case(name='cylinder2d', dim=2, dims=(nx, ny), mu=mu, lam=lam, u_inf=(u, 0.0), T_inf=T_inf,
                 method=method, kernel=kernel, ref_len=diameter, ref_area=diameter,
                 surface=math.pi * diameter, T_wall=T_w, steps=steps,
-                **_markers_common(X, n, T_DIRICHLET, T_w))
+                extra={'omega_star': omega_star}, **mk)
 
 
 def sphere_case(nx=384, ny=192, nz=192, diameter=32.0, center=None, mach=0.3, reynolds=100.0,
-                T_wall_ratio=None, method=METHOD_FODIBM_R, steps=5000, markers=None):
-    """3D sphere: adiabatic (T_wall_ratio None, theta_inf = 1) or isothermal wall."""
+                T_wall_ratio=None, method=METHOD_FODIBM_R, steps=5000, markers=None, omega_star=0.0):
+    """3D sphere: adiabatic (T_wall_ratio None, theta_inf = 1) or isothermal wall. With
+    omega_star it turns about the z axis at omega = 2 omega_star |u_inf| / D (Sec. 4, rotating
+    sphere: the equator moves at omega_star |u_inf|)."""
     if center is None:
         center = (0.3 * nx, ny / 2.0, nz / 2.0)
     if T_wall_ratio is None:
@@ -161,10 +184,13 @@ def sphere_case(nx=384, ny=192, nz=192, diameter=32.0, center=None, mach=0.3, re
     u, mu, lam = flow_units(mach, reynolds, diameter, T_inf)
     m = markers if markers is not None else int(round(math.pi * diameter * diameter))
     X, n = sphere_markers(center, diameter / 2.0, m)
+    mk = _markers_common(X, n, kind, tv)
+    if omega_star:
+        mk['u_wall'] = rotation_wall_velocity(X, center, 2.0 * omega_star * u / diameter)
     return Case(name='sphere3d', dim=3, dims=(nx, ny, nz), mu=mu, lam=lam, u_inf=(u, 0.0, 0.0),
                 T_inf=T_inf, method=method, ref_len=diameter, ref_area=math.pi * diameter ** 2 / 4,
                 surface=math.pi * diameter ** 2, T_wall=T_w, steps=steps,
-                **_markers_common(X, n, kind, tv))
+                extra={'omega_star': omega_star}, **mk)
 
 
 def config1(**kw):

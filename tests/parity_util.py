@@ -68,8 +68,8 @@ def rel(a, b):
 
 
 def small_sphere_case(method=wl.METHOD_FODIBM_R, T_wall_ratio=None, dims=(28, 22, 20), D=8.0, reynolds=50.0,
-                      mach=0.3, markers=None):
+                      mach=0.3, markers=None, omega_star=0.0):
     nx, ny, nz = dims
     return wl.sphere_case(nx=nx, ny=ny, nz=nz, diameter=D, center=(0.4 * nx + 0.23, ny / 2 + 0.17, nz / 2 - 0.11),
                           mach=mach, reynolds=reynolds, T_wall_ratio=T_wall_ratio, method=method, steps=1,
-                          markers=markers)
+                          markers=markers, omega_star=omega_star)

@@ -30,9 +30,10 @@ def lbmib():
     return mod
 
 
-def cylinder_small(method=wl.METHOD_FODIBM_R, bc='inflow_outflow', kernel=wl.KERNEL_COS):
+def cylinder_small(method=wl.METHOD_FODIBM_R, bc='inflow_outflow', kernel=wl.KERNEL_COS, omega_star=0.0,
+                   T_wall_ratio=1.2):
     c = wl.cylinder_case(nx=70, ny=44, center=(25.3, 21.7), diameter=14.0, markers=44, method=method,
-                         kernel=kernel, steps=1)
+                         kernel=kernel, steps=1, omega_star=omega_star, T_wall_ratio=T_wall_ratio)
     c.bc = bc
     return c
 
@@ -46,6 +47,11 @@ CASES = {
     'sph_R_adiabatic': lambda: small_sphere_case(),
     'sph_R_iso': lambda: small_sphere_case(T_wall_ratio=1.5),
     'sph_F_iso_per': lambda: _periodic(small_sphere_case(wl.METHOD_FODIBM, T_wall_ratio=1.2)),
+    # turning bodies (wall velocity omega e_z x (X - c)) in the three methods
+    'cyl_R_rot': lambda: cylinder_small(omega_star=0.6),
+    'cyl_F_rot_adiabatic': lambda: cylinder_small(wl.METHOD_FODIBM, omega_star=-0.4, T_wall_ratio=None),
+    'cyl_D_rot': lambda: cylinder_small(wl.METHOD_DIBM, omega_star=0.3),
+    'sph_R_rot': lambda: small_sphere_case(omega_star=0.6),
 }
 
 
@@ -124,7 +130,7 @@ def test_one_step_fp64_parity(lbmib, name, sweep):
 
 
 @pytest.mark.parametrize('sweep', list(SWEEPS))
-@pytest.mark.parametrize('name', ['cyl_R_io', 'sph_R_iso'])
+@pytest.mark.parametrize('name', ['cyl_R_io', 'sph_R_iso', 'cyl_R_rot', 'cyl_F_rot_adiabatic', 'sph_R_rot'])
 def test_multi_step_fp64_parity_and_loads(lbmib, name, sweep):
     case = CASES[name]()
     lat = for_dim(case.dim)

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import ib
+from paper_2607_07432_amd import workloads as wl
 
 GOLD = os.path.join(os.path.dirname(__file__), 'golden')
 
@@ -107,6 +108,48 @@ def test_linear_profile_reconstruction_exact():
     mid = [l for l in range(len(X)) if 12 <= X[l, 0] <= nx - 13]
     assert np.allclose(mf['uP'][mid, 0], 1.5 * a, rtol=0, atol=1e-14)
     assert np.allclose(mf['ut'][mid, 0], -a * g.dBV[mid], rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize('method', [ib.FODIBM_R, ib.FODIBM, ib.DIBM])
+def test_moving_wall_targets(method):
+    # Wall sliding at U_w along x over a linear profile u = U_w + a s (Couette flow): Eq. (27)
+    # extrapolates from the wall velocity, u^Vt = U_w - a d_BV (exact for the profile), while
+    # FODIBM and DIBM impose u^Bt = U_w itself (Eqs. (20)-(22)); the Lagrangian force of a fluid
+    # carried by the wall is then 2 rho (u^t - u*) and W^IB = rho (|u^t|^2 - |u*|^2) / 2.
+    nx, ny, y0, a, Uw, rho0 = 40, 16, 8.0, 0.21, 0.05, 1.3
+    X = np.array([[float(x), y0] for x in range(4, nx - 4)])
+    n = np.tile([0.0, 1.0], (len(X), 1))
+    g = ib.build_geometry((nx, ny), X, n, method)
+    ys = np.repeat(np.arange(ny), nx).astype(float)
+    u = np.stack([Uw + a * (ys - y0), np.zeros(nx * ny)])
+    mk = ib.Markers(u_wall=np.tile([Uw, 0.0], (len(X), 1)), t_kind=np.zeros(len(X), int),
+                    t_value=np.zeros(len(X)))
+    rho = np.full(nx * ny, rho0)
+    mf = ib.marker_forces(g, mk, _Prm(), rho, rho * u, u, np.ones(nx * ny))
+    mid = [l for l in range(len(X)) if 12 <= X[l, 0] <= nx - 13]
+    if method == ib.FODIBM_R:
+        assert np.allclose(mf['uP'][mid, 0], Uw + 1.5 * a, rtol=0, atol=1e-14)
+        expect = Uw - a * g.dBV[mid]
+    else:
+        expect = np.full(len(mid), Uw)
+    assert np.allclose(mf['ut'][mid, 0], expect, rtol=0, atol=1e-14)
+    assert np.allclose(mf['ut'][mid, 1], 0.0, rtol=0, atol=1e-15)
+    ustar = mf['u'][mid, 0]
+    assert np.allclose(mf['rho'][mid], rho0, rtol=0, atol=1e-14)
+    assert np.allclose(mf['F'][mid, 0], 2 * rho0 * (expect - ustar), rtol=0, atol=1e-14)
+    assert np.allclose(mf['Wib'][mid], rho0 * (expect ** 2 - ustar ** 2) / 2, rtol=0, atol=1e-14)
+
+
+def test_rotating_wall_velocity():
+    # omega e_z x (X - c): tangential to the circle, of magnitude omega R, counter-clockwise
+    c, R, om = (30.2, 20.7), 7.0, 0.013
+    X, n = wl.cylinder_markers(c, R, 40)
+    u = wl.rotation_wall_velocity(X, c, om)
+    assert np.allclose((u * n).sum(axis=1), 0.0, atol=1e-15)
+    assert np.allclose(np.linalg.norm(u, axis=1), om * R, rtol=1e-12)
+    assert np.all(n[:, 0] * u[:, 1] - n[:, 1] * u[:, 0] > 0)
+    case = wl.cylinder_case(omega_star=0.5)
+    assert np.allclose(np.linalg.norm(case.u_wall, axis=1), 0.5 * case.u_ref, rtol=1e-12)
 
 
 class _Prm:
