@@ -168,15 +168,19 @@ def bench_learned(args):
     """Learned warm start on 256 x 128 ellipses: solver-generated steady data, training, and the
     time to steady state (FP64, r < 1e-7) warm vs cold on held-out seeds."""
     from paper_2607_07432_amd import learned
-    ev = learned.main(['--train', str(args.train_cases), '--heldout', str(args.heldout_cases),
-                       '--epochs', str(args.epochs)])
+    argv = ['--train', str(args.train_cases), '--heldout', str(args.heldout_cases), '--epochs', str(args.epochs),
+            '--shape', args.shape]
+    if args.eval_shapes:
+        argv += ['--eval-shapes', args.eval_shapes]
+    ev = learned.main(argv)
     out = {
-        'metric': 'time-to-steady warm vs cold at L2 residual 1e-7 (FP64), 256x128 ellipses',
+        'metric': f'time-to-steady warm vs cold at L2 residual 1e-7 (FP64), 256x128 {ev["eval_shape"]}s',
         'value': round(ev['speedup_wall'], 4), 'unit': 'x (cold wall time / warm wall time incl. inference)',
         'n_gpus': 1, 'steps': None, 'warmup': 0, 'ms_per_step': None, 'higher_is_better': True,
         'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64 solver, bf16 network', 'data': 'synthetic',
-        'config': {'workload': f'learned: {args.train_cases} training seeds, {args.heldout_cases} held-out seeds, '
-                               f'{args.epochs} epochs, 5-level U-Net 32..256 channels'},
+        'config': {'workload': f'learned: {args.train_cases} training seeds ({args.shape}), {args.heldout_cases} '
+                               f'held-out seeds ({ev["eval_shape"]}), {args.epochs} epochs, 5-level U-Net 32..256 '
+                               'channels'},
         'roofline': {'bound': 'mfma', 'kernel': 'U-Net training step (forward + backward + Adam), batch 16',
                      'achieved': round(ev['train_tflops'], 2), 'peak': 2500.0, 'unit': 'TFLOP/s',
                      'frac': round(ev['train_tflops'] / 2500.0, 4), 'traffic': None},
@@ -233,6 +237,9 @@ def main():
     ap.add_argument('--train-cases', type=int, default=2000)
     ap.add_argument('--heldout-cases', type=int, default=512)
     ap.add_argument('--epochs', type=int, default=80)
+    ap.add_argument('--shape', choices=('ellipse', 'star', 'mixed'), default='ellipse',
+                    help='learned workload: bodies of the training cases')
+    ap.add_argument('--eval-shapes', default=None, help='learned workload: bodies of the held-out cases')
     args = ap.parse_args()
 
     if args.gpus != 1:

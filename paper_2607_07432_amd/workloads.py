@@ -249,23 +249,71 @@ def batched_cases(count=64, seed0=1000, steps=2000, m_lo=64, m_hi=256, kappa_max
 
 
 def learned_cases(count, seed0=0, nx=256, ny=128, m=64, mach=(0.05, 0.15), reynolds=(15.0, 35.0),
-                  kappa_max=0.11):
-    """Cases of the learned warm start: one ellipse of perimeter m on nx x ny, seed s drawn from
-    PCG64(seed0 + s): aspect U[1,4], angle U[0,90 deg], Ma and Re uniform in the given ranges
-    (redrawn while the conduction number exceeds kappa_max), adiabatic no-slip wall."""
+                  kappa_max=0.11, shape='ellipse'):
+    """Cases of the learned warm start: one body of perimeter m on nx x ny, seed s drawn from
+    PCG64(seed0 + s), adiabatic no-slip wall, Ma and Re uniform in the given ranges (redrawn
+    while the conduction number exceeds kappa_max).
+      shape 'ellipse': aspect U[1,4], angle U[0,90 deg];
+      shape 'star': 5-point star of Eq. (39) with dr/D U[0,0.1], angle U[0,72 deg];
+      shape 'mixed': even seeds ellipses, odd seeds stars."""
     cases = []
     for s in range(count):
         rng = np.random.Generator(np.random.PCG64(seed0 + s))
-        aspect = rng.uniform(1.0, 4.0)
-        angle = math.radians(rng.uniform(0.0, 90.0))
+        kind = shape if shape != 'mixed' else ('ellipse' if (seed0 + s) % 2 == 0 else 'star')
+        if kind == 'ellipse':
+            aspect = rng.uniform(1.0, 4.0)
+            angle = math.radians(rng.uniform(0.0, 90.0))
+        elif kind == 'star':
+            dr_D = rng.uniform(0.0, 0.1)
+            angle = math.radians(rng.uniform(0.0, 72.0))
+        else:
+            raise ValueError(f'unknown shape {shape}')
         while True:
             ma = rng.uniform(*mach)
             re = rng.uniform(*reynolds)
-            c = ellipse_case(m, aspect, angle, ma, re, None, nx=nx, ny=ny, name=f'learn{seed0 + s}')
+            if kind == 'ellipse':
+                c = ellipse_case(m, aspect, angle, ma, re, None, nx=nx, ny=ny, name=f'learn{seed0 + s}')
+            else:
+                c = star_case(m, dr_D, angle, ma, re, None, nx=nx, ny=ny, name=f'star{seed0 + s}')
             if conduction_number(c) <= kappa_max:
                 break
         cases.append(c)
     return cases
+
+
+def star_perimeter(r0, dr, dense=20000):
+    t = 2.0 * np.pi * np.arange(dense) / dense
+    r = r0 + dr * np.cos(5 * t)
+    drdt = -5 * dr * np.sin(5 * t)
+    return float(np.sum(np.hypot(r, drdt)) * 2.0 * np.pi / dense)
+
+
+def star_case(m, dr_over_D, angle, mach, reynolds, T_wall_ratio=None, steps=2000, name='star', nx=None, ny=None):
+    """Five-point star of Eq. (39) (r = r0 + dr cos 5t, D = 2 r0, dr = dr_over_D D) of perimeter
+    m dx with m markers, turned by angle, centre (0.3 nx, 0.5 ny), no-slip wall; walls as in
+    ellipse_case. Re and Ma are based on D."""
+    nx = nx if nx is not None else 4 * m
+    ny = ny if ny is not None else nx // 2
+    r0 = m / star_perimeter(1.0, 2.0 * dr_over_D)       # perimeter scales with r0
+    dr = 2.0 * dr_over_D * r0
+    if T_wall_ratio is None:
+        T_inf = T_w = 1.0
+        kind, value = T_NEUMANN, 0.0
+    else:
+        T_inf, T_w = reference_temperatures(T_wall_ratio)
+        kind, value = T_DIRICHLET, T_w
+    D = 2.0 * r0
+    u, mu, lam = flow_units(mach, reynolds, D, T_inf)
+    c0 = (0.3 * nx, 0.5 * ny)
+    X0, n0 = star_markers((0.0, 0.0), r0, dr, m)
+    ca, sa = math.cos(angle), math.sin(angle)
+    rot = np.array([[ca, -sa], [sa, ca]])
+    X = X0 @ rot.T + np.array(c0)
+    n = n0 @ rot.T
+    return Case(name=name, dim=2, dims=(nx, ny), mu=mu, lam=lam, u_inf=(u, 0.0), T_inf=T_inf,
+                ref_len=D, ref_area=D, surface=m, T_wall=T_w, steps=steps,
+                extra=dict(r0=r0, dr=dr, angle=angle, mach=mach, reynolds=reynolds, center=c0, shape='star'),
+                **_markers_common(X, n, kind, value))
 
 
 def ellipse_case(m, aspect, angle, mach, reynolds, T_wall_ratio=None, steps=2000, name='ellipse',

@@ -52,6 +52,8 @@ CASES = {
     'cyl_F_rot_adiabatic': lambda: cylinder_small(wl.METHOD_FODIBM, omega_star=-0.4, T_wall_ratio=None),
     'cyl_D_rot': lambda: cylinder_small(wl.METHOD_DIBM, omega_star=0.3),
     'sph_R_rot': lambda: small_sphere_case(omega_star=0.6),
+    # non-convex body: 5-point star of Eq. (39)
+    'star_R': lambda: wl.star_case(48, 0.1, 0.3, 0.15, 30.0, nx=72, ny=48, steps=1),
 }
 
 

@@ -210,6 +210,40 @@ def test_lists_match_brute_force(D):
             assert sorted(g.supp_lin[l].tolist()) == bf[l]
 
 
+def test_star_lists_match_brute_force():
+    # the non-convex 5-point star of Eq. (39), turned by 0.4 rad
+    c = wl.star_case(40, 0.1, 0.4, 0.1, 20.0, nx=28, ny=26)
+    g = ib.build_geometry(c.dims, c.X, c.n, ib.FODIBM_R)
+    bf = brute_geometry(c.dims, c.X.tolist(), c.n.tolist(), True)
+    assert sum(len(v) for v in bf.values()) > 0
+    for l in range(len(c.X)):
+        assert sorted(g.supp_lin[l].tolist()) == bf[l]
+
+
+def test_star_interior_equals_polar_test():
+    # Candidate nodes (within a marker's support box) that lie 0.3 .. 1.4 from the surface along
+    # the ray from the centre are interior exactly when r < r0 + dr cos 5t in the star's polar
+    # coordinates (dense markers, so the nearest-marker test resolves the surface).
+    c = wl.star_case(160, 0.1, 0.0, 0.1, 20.0, nx=80, ny=60)
+    g = ib.build_geometry(c.dims, c.X, c.n, ib.FODIBM_R)
+    r0, dr = c.extra['r0'], c.extra['dr']
+    cx, cy = c.extra['center']
+    inside = set(g.interior_lin.tolist())
+    checked = 0
+    for y in range(c.dims[1]):
+        for x in range(c.dims[0]):
+            px, py = x - cx, y - cy
+            r, t = math.hypot(px, py), math.atan2(py, px)
+            rs = r0 + dr * math.cos(5 * t)
+            if not 0.3 < abs(r - rs) < 1.4:
+                continue
+            if not np.any(np.all(np.abs(c.X - np.array([x, y])) < 2.0, axis=1)):
+                continue
+            checked += 1
+            assert ((x + c.dims[0] * y) in inside) == (r < rs)
+    assert checked > 100
+
+
 def test_cylinder_interior_equals_closed_disk():
     # The 63-marker cylinder D = 20 at (60, 50): nearest-marker interior test equals |x - c| <= R.
     t = 2 * np.pi * np.arange(63) / 63
