@@ -50,7 +50,7 @@ enum { LBM_SWEEP_FUSED = 0, LBM_SWEEP_THREE_PASS = 1 };
 /* Problem parameters (lattice units). Sec. 2.1 (gas), Sec. 2.2 (solver), Sec. 3.4 (gamma). */
 typedef struct lbm_params {
     int dim;            /* 2 (D2Q9) or 3 (D3Q19, Appendix A) */
-    int nx, ny, nz;     /* grid size; nz = 1 when dim = 2 */
+    int nx, ny, nz;     /* grid size: nx >= 5, ny >= 2, nz >= 2 in 3D and nz = 1 in 2D */
     int precision;      /* LBM_F32 or LBM_F64: storage and arithmetic of the sweep */
     int bc_x;           /* LBM_BC_PERIODIC or LBM_BC_INFLOW_OUTFLOW along x (y, z periodic) */
     int kernel;         /* marker kernel: LBM_KERNEL_COS (Eq. (19), d = 2) or LBM_KERNEL_ROMA3 */

@@ -174,7 +174,11 @@ namespace {
 int validate_params(const lbm_params* p, std::string& why) {
     if (!p) return why = "params is NULL", LBM_E_INVAL;
     if (p->dim != 2 && p->dim != 3) return why = "dim must be 2 or 3", LBM_E_INVAL;
-    if (p->nx < 5 || p->ny < 1 || p->nz < 1) return why = "grid too small (nx >= 5)", LBM_E_INVAL;
+    // Stencils reach two nodes along every axis and the periodic wraps add or subtract the axis
+    // length once, so every active axis holds at least two nodes; x also holds the two inflow
+    // and two outflow columns of the domain closure plus one interior column.
+    if (p->nx < 5 || p->ny < 2 || p->nz < 1 || (p->dim == 3 && p->nz < 2))
+        return why = "grid too small (nx >= 5, ny >= 2, and nz >= 2 in 3D)", LBM_E_INVAL;
     if (p->dim == 2 && p->nz != 1) return why = "nz must be 1 in 2D", LBM_E_INVAL;
     if (p->precision != LBM_F32 && p->precision != LBM_F64) return why = "precision must be 32 or 64", LBM_E_INVAL;
     if (p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_INFLOW_OUTFLOW) return why = "bad bc_x", LBM_E_INVAL;

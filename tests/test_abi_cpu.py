@@ -54,6 +54,12 @@ def test_workspace_bytes_is_pure_and_validates():
     bad.mu = -1.0
     assert lib.lbm_workspace_bytes(ctypes.byref(bad)) == 0
     assert lib.lbm_workspace_bytes(None) == 0
+    # every active axis needs two nodes (x: five) and 2D grids have nz = 1
+    for nx, ny, nz, dim, ok in ((5, 2, 1, 2, True), (4, 8, 1, 2, False), (6, 1, 1, 2, False), (6, 4, 2, 2, False),
+                                (5, 2, 2, 3, True), (6, 5, 1, 3, False), (6, 1, 5, 3, False)):
+        q = lbmib.params_from_case(case)
+        q.nx, q.ny, q.nz, q.dim = nx, ny, nz, dim
+        assert (lib.lbm_workspace_bytes(ctypes.byref(q)) > 0) == ok, (nx, ny, nz, dim)
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
