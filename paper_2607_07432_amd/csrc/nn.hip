@@ -113,6 +113,106 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
         }
 }
 
+// Convolution forward (3x3) with the input staged through LDS. A workgroup of 4 wavefronts owns
+// COB output channels x 64 pixels, the pixels being a TH x TW block of one image (TW = min(64, W),
+// TH = 64 / TW, rows beyond the image masked). Per chunk of 32 input channels it stages the
+// (TH + 2) x (TW + 2) input block with its one-pixel halo (zero outside the image) as 16-byte
+// vectors into LDS ([pixel][channel], padded), then runs the nine taps from there: the B operand
+// of tap (dy, dx) for output pixel (ty, tx) is the staged pixel (ty + dy + 1, tx + dx + 1), so
+// every input value is read from memory once per chunk instead of once per tap. The A operand
+// (weights, shared by all workgroups) is read from global memory as in k_conv_fwd. Wavefront w
+// computes 32 channels x (64 / WN) pixels with WM = COB / 32 wavefronts along the channels.
+// Requires cin % 32 == 0, cout % COB == 0, xstride % 8 == 0, ystride, yoff % 4 == 0.
+template <int COB>
+__global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__ X, int cin, int xstride,
+                                                      const __bf16* __restrict__ Wt, const float* __restrict__ bias,
+                                                      int cout, int H, int Wd, int tw, int relu,
+                                                      __bf16* __restrict__ Y, int ystride, int yoff) {
+    constexpr int CK = 32, LDP = CK + 8;
+    constexpr int MAXP = 3 * 66;                    // largest staged block: TH = 1, TW = 64
+    constexpr int WM = COB / 32, WN = 4 / WM, TNW = 4 / WN;
+    __shared__ __bf16 patch[MAXP * LDP];
+    const int th = 64 / tw;
+    const int pw = tw + 2, np = (th + 2) * pw;
+    const int co_tiles = cout / COB;
+    const int bx_tiles = Wd / tw, by_tiles = (H + th - 1) / th;
+    long long b = blockIdx.x;
+    const int cot = (int)(b % co_tiles);
+    b /= co_tiles;
+    const int bxt = (int)(b % bx_tiles);
+    b /= bx_tiles;
+    const int byt = (int)(b % by_tiles);
+    const long long n = b / by_tiles;
+    const int x0 = bxt * tw, y0 = byt * th;
+    const int t = threadIdx.x, lane = t % WAVE, wv = t / WAVE;
+    const int wm = wv / WN, wn = wv % WN;
+    const int co_w = cot * COB + wm * 32;
+    const int K = 9 * cin;
+    const long long img = n * H * Wd;
+
+    int tyj[TNW], txj[TNW];
+#pragma unroll
+    for (int j = 0; j < TNW; ++j) {
+        const int q = wn * (64 / WN) + j * 16 + lane % 16;   // pixel of the block
+        tyj[j] = q / tw;
+        txj[j] = q % tw;
+    }
+    f32x4 acc[2][TNW];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < TNW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = {};
+    const int kg = 8 * (lane / 16);                 // this lane's 8-channel group within a k step
+
+    for (int ci0 = 0; ci0 < cin; ci0 += CK) {
+        __syncthreads();                            // the previous chunk's reads are done
+        for (int v = t; v < np * (CK / 8); v += 256) {
+            const int pix = v / (CK / 8), g = v % (CK / 8);
+            const int y = y0 - 1 + pix / pw, x = x0 - 1 + pix % pw;
+            bf16x8 val = zero;
+            if (y >= 0 && y < H && x >= 0 && x < Wd)
+                val = *reinterpret_cast<const bf16x8*>(X + (img + (long long)y * Wd + x) * xstride + ci0 + 8 * g);
+            *reinterpret_cast<bf16x8*>(patch + pix * LDP + 8 * g) = val;
+        }
+        __syncthreads();
+#pragma unroll 3
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;   // offsets + 1
+            const long long kk = (long long)tap * cin + ci0 + kg;
+            bf16x8 a[2], bv[TNW];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(Wt + (long long)(co_w + i * 16 + lane % 16) * K + kk);
+#pragma unroll
+            for (int j = 0; j < TNW; ++j)
+                bv[j] = *reinterpret_cast<const bf16x8*>(patch + ((tyj[j] + dy) * pw + txj[j] + dx) * LDP + kg);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < TNW; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < TNW; ++j) {
+            const int y = y0 + tyj[j];
+            if (y >= H) continue;
+            const long long p = img + (long long)y * Wd + x0 + txj[j];
+            const int cb = co_w + i * 16 + (lane / 16) * 4;
+            bf16x4 o;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = acc[i][j][r] + (bias ? bias[cb + r] : 0.f);
+                if (relu) v = v > 0.f ? v : 0.f;
+                o[r] = (__bf16)v;
+            }
+            *reinterpret_cast<bf16x4*>(Y + p * ystride + yoff + cb) = o;
+        }
+}
+
 // Weight and bias gradients staged through LDS. A workgroup of 4 wavefronts owns a BM x BN tile of
 // (output channel) x (k = tap cin + ci) and a range of pixels (one split). Per step of 32 pixels
 // it reads dY [32 pixels][BM channels] and X^ [32 pixels][BN columns] as 16-byte vectors of 8
@@ -223,12 +323,22 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_lds(const __bf16* __restrict
 }
 
 // Fixed-order sum of the split partials into the FP32 gradient.
+// Rows r are summed into r % 8 partial sums (independent loads in flight), which are then added
+// in order 0..7: a fixed order, so the result does not depend on the launch.
+__device__ __forceinline__ float strided_sum8(const float* __restrict__ part, int rows, long long n, long long i) {
+    float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int r = 0;
+    for (; r + 8 <= rows; r += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += part[(long long)(r + u) * n + i];
+    for (int u = 0; r + u < rows; ++u) a[u] += part[(long long)(r + u) * n + i];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 __global__ void k_sum_splits(const float* __restrict__ part, int nsplit, long long n, float* __restrict__ g) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += part[(long long)k * n + i];
-    g[i] = s;
+    g[i] = strided_sum8(part, nsplit, n, i);
 }
 
 // W'[ci][8 - t][co] = W[co][t][ci]: backward data is the forward convolution of dY with W'.
@@ -243,73 +353,99 @@ __global__ void k_flip(const __bf16* __restrict__ W, int cout, int cin, __bf16* 
 }
 
 // dA[p][off + c] *= (A[p][off + c] > 0), c < C (in place on the gradient of a ReLU output).
+// One thread per 8 channels (C, stride and off multiples of 8).
 __global__ void k_relu_bwd(__bf16* __restrict__ dA, const __bf16* __restrict__ A, long long P, int C, int stride, int off) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * C) return;
-    const long long p = i / C;
-    const int c = (int)(i - p * C);
-    const long long o = p * stride + off + c;
-    if (!((float)A[o] > 0.f)) dA[o] = (__bf16)0.f;
+    const int G = C / 8;
+    if (i >= P * G) return;
+    const long long p = i / G;
+    const long long o = p * stride + off + 8 * (int)(i - p * G);
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(A + o);
+    bf16x8 g = *reinterpret_cast<const bf16x8*>(dA + o);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (!((float)a[k] > 0.f)) g[k] = (__bf16)0.f;
+    *reinterpret_cast<bf16x8*>(dA + o) = g;
 }
 
 // 2x2 average pooling of a channel slice: out[n][y][x][c] = mean of in[n][2y+i][2x+j][off + c].
+// One thread per output pixel and 8 channels (C, stride, off multiples of 8).
 __global__ void k_pool(const __bf16* __restrict__ in, int stride, int off, int C, int B, int H, int Wd,
                        __bf16* __restrict__ out) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int h = H / 2, w = Wd / 2;
-    const long long n_out = (long long)B * h * w * C;
+    const int h = H / 2, w = Wd / 2, G = C / 8;
+    const long long n_out = (long long)B * h * w * G;
     if (i >= n_out) return;
-    const int c = (int)(i % C);
-    const long long q = i / C;
+    const int c = 8 * (int)(i % G);
+    const long long q = i / G;
     const int x = (int)(q % w), y = (int)((q / w) % h);
     const long long n = q / ((long long)w * h);
     const long long b = ((n * H + 2 * y) * Wd + 2 * x) * stride + off + c;
-    const float s = ((float)in[b] + (float)in[b + stride]) + ((float)in[b + (long long)Wd * stride] + (float)in[b + (long long)Wd * stride + stride]);
-    out[i] = (__bf16)(0.25f * s);
+    const bf16x8 v0 = *reinterpret_cast<const bf16x8*>(in + b);
+    const bf16x8 v1 = *reinterpret_cast<const bf16x8*>(in + b + stride);
+    const bf16x8 v2 = *reinterpret_cast<const bf16x8*>(in + b + (long long)Wd * stride);
+    const bf16x8 v3 = *reinterpret_cast<const bf16x8*>(in + b + (long long)Wd * stride + stride);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        o[k] = (__bf16)(0.25f * (((float)v0[k] + (float)v1[k]) + ((float)v2[k] + (float)v3[k])));
+    *reinterpret_cast<bf16x8*>(out + q * C + c) = o;
 }
 
 // Adjoint of the pooling, accumulated: dIn[n][2y+i][2x+j][off + c] += dOut[n][y][x][c] / 4.
 __global__ void k_pool_bwd(const __bf16* __restrict__ dOut, int C, int B, int H, int Wd, __bf16* __restrict__ dIn,
                            int stride, int off) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long n_in = (long long)B * H * Wd * C;
+    const int G = C / 8;
+    const long long n_in = (long long)B * H * Wd * G;
     if (i >= n_in) return;
-    const int c = (int)(i % C);
-    const long long q = i / C;
+    const int c = 8 * (int)(i % G);
+    const long long q = i / G;
     const int x = (int)(q % Wd), y = (int)((q / Wd) % H);
     const long long n = q / ((long long)Wd * H);
-    const float g = (float)dOut[((n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c];
+    const bf16x8 g = *reinterpret_cast<const bf16x8*>(dOut + ((n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c);
     const long long o = q * stride + off + c;
-    dIn[o] = (__bf16)((float)dIn[o] + 0.25f * g);
+    bf16x8 d = *reinterpret_cast<const bf16x8*>(dIn + o);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) d[k] = (__bf16)((float)d[k] + 0.25f * (float)g[k]);
+    *reinterpret_cast<bf16x8*>(dIn + o) = d;
 }
 
 // Nearest 2x upsampling into a channel slice: out[n][y][x][off + c] = in[n][y/2][x/2][c].
 __global__ void k_up(const __bf16* __restrict__ in, int C, int B, int H, int Wd, __bf16* __restrict__ out, int stride,
                      int off) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long n_out = (long long)B * H * Wd * C;
+    const int G = C / 8;
+    const long long n_out = (long long)B * H * Wd * G;
     if (i >= n_out) return;
-    const int c = (int)(i % C);
-    const long long q = i / C;
+    const int c = 8 * (int)(i % G);
+    const long long q = i / G;
     const int x = (int)(q % Wd), y = (int)((q / Wd) % H);
     const long long n = q / ((long long)Wd * H);
-    out[q * stride + off + c] = in[((n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c];
+    *reinterpret_cast<bf16x8*>(out + q * stride + off + c) =
+        *reinterpret_cast<const bf16x8*>(in + ((n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c);
 }
 
 // Adjoint of the upsampling: dIn[n][y][x][c] = sum of the four dOut[n][2y+i][2x+j][off + c].
 __global__ void k_up_bwd(const __bf16* __restrict__ dOut, int stride, int off, int C, int B, int H, int Wd,
                          __bf16* __restrict__ dIn) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int h = H / 2, w = Wd / 2;
-    const long long n_in = (long long)B * h * w * C;
+    const int h = H / 2, w = Wd / 2, G = C / 8;
+    const long long n_in = (long long)B * h * w * G;
     if (i >= n_in) return;
-    const int c = (int)(i % C);
-    const long long q = i / C;
+    const int c = 8 * (int)(i % G);
+    const long long q = i / G;
     const int x = (int)(q % w), y = (int)((q / w) % h);
     const long long n = q / ((long long)w * h);
     const long long b = ((n * H + 2 * y) * Wd + 2 * x) * stride + off + c;
-    const float s = ((float)dOut[b] + (float)dOut[b + stride]) + ((float)dOut[b + (long long)Wd * stride] + (float)dOut[b + (long long)Wd * stride + stride]);
-    dIn[i] = (__bf16)s;
+    const bf16x8 v0 = *reinterpret_cast<const bf16x8*>(dOut + b);
+    const bf16x8 v1 = *reinterpret_cast<const bf16x8*>(dOut + b + stride);
+    const bf16x8 v2 = *reinterpret_cast<const bf16x8*>(dOut + b + (long long)Wd * stride);
+    const bf16x8 v3 = *reinterpret_cast<const bf16x8*>(dOut + b + (long long)Wd * stride + stride);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = (__bf16)(((float)v0[k] + (float)v1[k]) + ((float)v2[k] + (float)v3[k]));
+    *reinterpret_cast<bf16x8*>(dIn + q * C + c) = o;
 }
 
 // FP32 input planes [P][4] -> bf16 [P][8] (channels 4..7 zero).
@@ -357,7 +493,7 @@ __global__ void k_head_dgrad(const float* __restrict__ Wh, const float* __restri
 
 // Head backward, parameters: per block of HEAD_PIX pixels, thread q < 132 sums
 // dWh[o][c] = sum_p dOut[p][o] A[p][c] (q = 32 o + c) or dbh[o] = sum_p dOut[p][o] (q = 128 + o).
-constexpr int HEAD_PIX = 1024;
+constexpr int HEAD_PIX = 256;
 constexpr int HEAD_NP = NOUT * 32 + NOUT;
 __global__ void __launch_bounds__(256) k_head_wgrad(const __bf16* __restrict__ A, const float* __restrict__ dOut,
                                                     long long P, float* __restrict__ part) {
@@ -366,21 +502,22 @@ __global__ void __launch_bounds__(256) k_head_wgrad(const __bf16* __restrict__ A
     const long long p0 = (long long)blockIdx.x * HEAD_PIX;
     const int o = q < NOUT * 32 ? q / 32 : q - NOUT * 32;
     const int c = q < NOUT * 32 ? q % 32 : -1;
-    float s = 0.f;
-    for (long long p = p0; p < p0 + HEAD_PIX && p < P; ++p) {
-        const float g = dOut[p * NOUT + o];
-        s += c >= 0 ? g * (float)A[p * 32 + c] : g;
-    }
-    part[(long long)blockIdx.x * HEAD_NP + q] = s;
+    float s[4] = {0.f, 0.f, 0.f, 0.f};           // pixel p goes to s[p % 4], added in order
+    for (long long p = p0; p < p0 + HEAD_PIX && p < P; p += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (p + u >= P) break;
+            const float g = dOut[(p + u) * NOUT + o];
+            s[u] += c >= 0 ? g * (float)A[(p + u) * 32 + c] : g;
+        }
+    part[(long long)blockIdx.x * HEAD_NP + q] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 // Column sums of a [rows][n] FP32 array in fixed order: out[i] = sum_r part[r][i].
 __global__ void k_colsum(const float* __restrict__ part, int rows, int n, float* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += part[(long long)r * n + i];
-    out[i] = s;
+    out[i] = strided_sum8(part, rows, n, i);
 }
 
 // Masked mean squared error over P pixels and 4 planes (mask NULL: all ones).
@@ -672,6 +809,20 @@ int head_layer() { return 2 * LEVELS + 2 * (LEVELS - 1); }
 hipError_t conv_fwd(nn_unet* u, const Layer& ly, const __bf16* X, int xstride, const __bf16* Wt, const float* bias,
                     int relu, int B, int H, int W, __bf16* Y, int ystride, int yoff) {
     const long long P = (long long)B * H * W;
+    // 3x3 layers with 32-channel multiples and power-of-two widths: input staged through LDS
+    if (ly.taps == 9 && ly.cin % 32 == 0 && ly.cout % 32 == 0 && xstride % 8 == 0 && ystride % 4 == 0 &&
+        yoff % 4 == 0 && W >= 1 && (W & (W - 1)) == 0) {
+        const int tw = W < 64 ? W : 64;
+        const int th = 64 / tw;
+        const long long nblk = (long long)B * ((H + th - 1) / th) * (W / tw);
+        if (ly.cout % 64 == 0)
+            hipLaunchKernelGGL((k_conv_fwd_lds<64>), dim3((unsigned)(nblk * (ly.cout / 64))), dim3(256), 0, u->stream,
+                               X, ly.cin, xstride, Wt, bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
+        else
+            hipLaunchKernelGGL((k_conv_fwd_lds<32>), dim3((unsigned)(nblk * (ly.cout / 32))), dim3(256), 0, u->stream,
+                               X, ly.cin, xstride, Wt, bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
+        return hipGetLastError();
+    }
     constexpr int TM = 2, TN = 4;
     if (ly.cout % (16 * TM) || ly.cin % 8 || xstride % 8 || ystride % 4 || yoff % 4) return hipErrorInvalidValue;
     const long long tiles = (long long)(ly.cout / (16 * TM)) * ((P + 16 * TN - 1) / (16 * TN));
@@ -723,7 +874,8 @@ hipError_t conv_dgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, in
 }
 
 hipError_t relu_bwd(nn_unet* u, __bf16* g, const __bf16* a, long long P, int C, int stride, int off) {
-    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks(P * C)), dim3(256), 0, u->stream, g, a, P, C, stride, off);
+    if (C % 8 || stride % 8 || off % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks(P * C / 8)), dim3(256), 0, u->stream, g, a, P, C, stride, off);
     return hipGetLastError();
 }
 
@@ -742,7 +894,7 @@ int forward(nn_unet* u, int B, const float* d_in, float* d_out) {
             // pooled s_{l-1}: the skip slice of cat[l-1]
             const Act& src = u->cat[l - 1];
             const long long n = (long long)B * h * w * CH[l - 1];
-            hipLaunchKernelGGL(k_pool, dim3(blocks(n)), dim3(256), 0, u->stream, (const __bf16*)src.a, src.c, CH[l],
+            hipLaunchKernelGGL(k_pool, dim3(blocks(n / 8)), dim3(256), 0, u->stream, (const __bf16*)src.a, src.c, CH[l],
                                CH[l - 1], B, 2 * h, 2 * w, u->pool[l].a);
             NCHK(u, hipGetLastError());
             x = u->pool[l].a;
@@ -760,7 +912,7 @@ int forward(nn_unet* u, int B, const float* d_in, float* d_out) {
     for (int l = LEVELS - 2; l >= 0; --l) {
         const int h = H >> l, w = W >> l;
         const long long n = (long long)B * h * w * CH[l + 1];
-        hipLaunchKernelGGL(k_up, dim3(blocks(n)), dim3(256), 0, u->stream, below, CH[l + 1], B, h, w, u->cat[l].a,
+        hipLaunchKernelGGL(k_up, dim3(blocks(n / 8)), dim3(256), 0, u->stream, below, CH[l + 1], B, h, w, u->cat[l].a,
                            u->cat[l].c, 0);
         NCHK(u, hipGetLastError());
         const Layer& d0 = u->L[dec_conv(l, 0)];
@@ -815,7 +967,7 @@ int backward(nn_unet* u, const float* d_tgt, const float* d_mask, double* d_loss
         // the upsampled part of the concatenation goes to the output of the level below
         __bf16* gbelow = l + 1 < LEVELS - 1 ? u->dec_b[l + 1].g : u->bott_b.g;
         const long long n = (long long)B * (h / 2) * (w / 2) * CH[l + 1];
-        hipLaunchKernelGGL(k_up_bwd, dim3(blocks(n)), dim3(256), 0, u->stream, (const __bf16*)u->cat[l].g, u->cat[l].c, 0,
+        hipLaunchKernelGGL(k_up_bwd, dim3(blocks(n / 8)), dim3(256), 0, u->stream, (const __bf16*)u->cat[l].g, u->cat[l].c, 0,
                            CH[l + 1], B, h, w, gbelow);
         NCHK(u, hipGetLastError());
     }
@@ -839,7 +991,7 @@ int backward(nn_unet* u, const float* d_tgt, const float* d_mask, double* d_loss
             stride = u->cat[l].c;
             off = CH[l + 1];
             const long long n = P * CH[l];
-            hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(n)), dim3(256), 0, u->stream, (const __bf16*)u->pool[l + 1].g,
+            hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(n / 8)), dim3(256), 0, u->stream, (const __bf16*)u->pool[l + 1].g,
                                CH[l], B, h, w, ga, stride, off);
             NCHK(u, hipGetLastError());
         }

@@ -169,12 +169,14 @@ def test_short_fit_reduces_loss(lbmib, net_case):
     smooth = np.stack([np.sin(xx + yy), np.cos(xx), 0.5 * np.sin(yy), xx * 0.1], axis=-1)
     tt = torch.tensor(np.broadcast_to(smooth, (B, H, W, 4)).astype(np.float32).copy(), device='cuda')
     losses = []
-    for it in range(1, 41):
+    for it in range(1, 121):
         net.forward(xt)
         losses.append(float(net.backward(tt)[0].item()))
         net.adam(1e-3, it)
-    print('losses', losses[0], losses[-1], flush=True)
-    assert np.isfinite(losses).all() and losses[-1] < 0.5 * losses[0]
+    print('losses', losses[0], losses[39], losses[-1], flush=True)
+    # the loss passes a plateau around iteration 30-40 whose exit depends on the rounding order of
+    # the accumulation; by iteration 120 it is at 2-3 % of its start
+    assert np.isfinite(losses).all() and losses[-1] < 0.1 * losses[0]
 
 
 def test_trained_network_shortens_time_to_steady(lbmib):
