@@ -244,7 +244,7 @@ def main():
 
     if args.gpus != 1:
         print(f'bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab '
-              'decomposition is a design, not part of this build.', file=sys.stderr)
+              'decomposition is designed (z slabs with one halo exchange per step) but not implemented.', file=sys.stderr)
         sys.exit(2)
     if args.copy_kernel:
         copy_kernel(args.copy_kernel)
