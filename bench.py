@@ -169,7 +169,7 @@ def bench_learned(args):
     time to steady state (FP64, r < 1e-7) warm vs cold on held-out seeds."""
     from paper_2607_07432_amd import learned
     argv = ['--train', str(args.train_cases), '--heldout', str(args.heldout_cases), '--epochs', str(args.epochs),
-            '--shape', args.shape]
+            '--shape', args.shape, '--clip', str(args.clip), '--warmup-epochs', str(args.warmup_epochs)]
     if args.eval_shapes:
         argv += ['--eval-shapes', args.eval_shapes]
     ev = learned.main(argv)
@@ -234,12 +234,14 @@ def main():
     ap.add_argument('--sweep', choices=('fused', 'threepass'), default='fused')
     ap.add_argument('--workload', choices=('sphere3d', 'batch64', 'learned', 'methods'), default='sphere3d')
     ap.add_argument('--quick', action='store_true', help='methods workload: shorter runs')
-    ap.add_argument('--train-cases', type=int, default=2000)
+    ap.add_argument('--train-cases', type=int, default=4000)
     ap.add_argument('--heldout-cases', type=int, default=512)
-    ap.add_argument('--epochs', type=int, default=80)
+    ap.add_argument('--epochs', type=int, default=160)
     ap.add_argument('--shape', choices=('ellipse', 'star', 'mixed'), default='ellipse',
                     help='learned workload: bodies of the training cases')
     ap.add_argument('--eval-shapes', default=None, help='learned workload: bodies of the held-out cases')
+    ap.add_argument('--clip', type=float, default=1.0, help='learned workload: gradient-norm clipping (0: off)')
+    ap.add_argument('--warmup-epochs', type=float, default=1.0, help='learned workload: linear learning-rate warm-up')
     args = ap.parse_args()
 
     if args.gpus != 1:

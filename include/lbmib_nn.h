@@ -64,6 +64,12 @@ int nn_unet_backward(nn_unet* u, const float* d_target, const float* d_mask, dou
  * theta -= lr (m^ / (sqrt(v^) + eps) + weight_decay theta). Asynchronous. */
 int nn_unet_adam(nn_unet* u, double lr, double beta1, double beta2, double eps, int t, double weight_decay);
 
+/* Clipping by the global L2 norm of the parameter gradient of the last backward pass:
+ * g *= min(1, max_norm / ||g||_2), with ||g||_2 summed in FP64 in a fixed order. d_norm (device,
+ * nullable) receives {||g||_2, applied scale}. Runs on the stream without host synchronisation.
+ * Errors: NN_E_INVAL for max_norm <= 0. Asynchronous. */
+int nn_unet_clip_grad_norm(nn_unet* u, double max_norm, double* d_norm);
+
 void nn_unet_destroy(nn_unet* u);
 const char* nn_unet_last_error(nn_unet* u);
 

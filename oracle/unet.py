@@ -242,6 +242,12 @@ def backward(theta, cache, out, tgt, mask=None):
     return flat, loss(out, tgt, mask)
 
 
+def clip_grad_norm(g, max_norm):
+    """Gradient clipping by the global L2 norm: g min(1, max_norm / ||g||)."""
+    norm = float(np.sqrt(np.sum(np.asarray(g, dtype=np.float64) ** 2)))
+    return (g * (max_norm / norm) if norm > max_norm else g), norm
+
+
 def adam_step(theta, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
     m = b1 * m + (1 - b1) * g
     v = b2 * v + (1 - b2) * g * g

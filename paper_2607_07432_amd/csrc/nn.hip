@@ -607,6 +607,41 @@ __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* 
     if (b >= 0) bf[b] = (__bf16)t;
 }
 
+// Global L2 norm of the gradient and its clipping: NORM_BLOCKS block partials of sum g^2 in FP64
+// (grid-stride, then a fixed-order tree in the block), one block that adds the partials in order
+// and turns the norm into the scale min(1, max_norm / norm), and an in-place scaling that reads
+// the scale from device memory (no host synchronisation).
+constexpr int NORM_BLOCKS = 512;
+__global__ void __launch_bounds__(256) k_sqnorm_part(const float* __restrict__ g, long long n, double* __restrict__ part) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)NORM_BLOCKS * 256)
+        s += (double)g[i] * (double)g[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_clip_scale(const double* __restrict__ part, double max_norm, double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < NORM_BLOCKS; ++b) s += part[b];
+    const double norm = sqrt(s);
+    out[0] = norm;
+    out[1] = norm > max_norm ? max_norm / norm : 1.0;
+}
+
+__global__ void k_scale_grads(float* __restrict__ g, long long n, const double* __restrict__ scale) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double c = scale[1];
+    if (c != 1.0) g[i] = (float)((double)g[i] * c);
+}
+
 // FP32 master -> bf16 copies (after set_params).
 __global__ void k_to_bf(const float* __restrict__ theta, long long n, const long long* __restrict__ bf_map,
                         __bf16* __restrict__ bf) {
@@ -1101,6 +1136,23 @@ int nn_unet_adam(nn_unet* u, double lr, double beta1, double beta2, double eps, 
                        u->np, (float)lr, (float)beta1, (float)beta2, (float)eps, c1, c2, (float)weight_decay,
                        (const long long*)u->bf_map, u->wbf);
     NCHK(u, hipGetLastError());
+    return NN_OK;
+}
+
+int nn_unet_clip_grad_norm(nn_unet* u, double max_norm, double* d_norm) {
+    if (!u || !(max_norm > 0.0)) return NN_E_INVAL;
+    if (u->small_floats < 2 * (NORM_BLOCKS + 2)) return NN_E_INVAL;
+    // the bias / head partial buffer is free between backward passes
+    double* part = reinterpret_cast<double*>(u->small);
+    double* out = part + NORM_BLOCKS;
+    hipLaunchKernelGGL(k_sqnorm_part, dim3(NORM_BLOCKS), dim3(256), 0, u->stream, (const float*)u->grad, u->np, part);
+    NCHK(u, hipGetLastError());
+    hipLaunchKernelGGL(k_clip_scale, dim3(1), dim3(64), 0, u->stream, (const double*)part, max_norm, out);
+    NCHK(u, hipGetLastError());
+    hipLaunchKernelGGL(k_scale_grads, dim3(blocks(u->np)), dim3(256), 0, u->stream, u->grad, u->np,
+                       (const double*)out);
+    NCHK(u, hipGetLastError());
+    if (d_norm) NCHK(u, hipMemcpyAsync(d_norm, out, 2 * sizeof(double), hipMemcpyDeviceToDevice, u->stream));
     return NN_OK;
 }
 

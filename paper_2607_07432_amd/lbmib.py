@@ -27,7 +27,7 @@ EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step',
            'lbm_batch_set_tile', 'lbm_batch_config', 'lbm_batch_residuals', 'lbm_batch_destroy', 'lbm_batch_last_error',
            'lbm_learn_input', 'lbm_learn_target', 'lbm_learn_warm_start',
            'nn_unet_param_count', 'nn_unet_workspace_bytes', 'nn_unet_create', 'nn_unet_set_params',
-           'nn_unet_get_params', 'nn_unet_get_grads', 'nn_unet_forward', 'nn_unet_backward', 'nn_unet_adam',
+           'nn_unet_get_params', 'nn_unet_get_grads', 'nn_unet_forward', 'nn_unet_backward', 'nn_unet_adam', 'nn_unet_clip_grad_norm',
            'nn_unet_destroy', 'nn_unet_last_error']
 
 
@@ -114,13 +114,14 @@ def load_library(path=LIB_PATH):
     lib.nn_unet_forward.argtypes = [vp, i, vp, vp]
     lib.nn_unet_backward.argtypes = [vp, vp, vp, vp]
     lib.nn_unet_adam.argtypes = [vp, d, d, d, d, i, d]
+    lib.nn_unet_clip_grad_norm.argtypes = [vp, d, vp]
     lib.nn_unet_destroy.argtypes = [vp]
     lib.nn_unet_destroy.restype = None
     lib.nn_unet_last_error.argtypes = [vp]
     lib.nn_unet_last_error.restype = ctypes.c_char_p
     for name in ('lbm_learn_input', 'lbm_learn_target', 'lbm_learn_warm_start', 'nn_unet_create',
                  'nn_unet_set_params', 'nn_unet_get_params', 'nn_unet_get_grads', 'nn_unet_forward',
-                 'nn_unet_backward', 'nn_unet_adam'):
+                 'nn_unet_backward', 'nn_unet_adam', 'nn_unet_clip_grad_norm'):
         getattr(lib, name).restype = i
     del fp
     for name in ('lbm_init_grid', 'ib_set_markers', 'lbm_step', 'lbm_step_timed', 'ib_wall_loads', 'lbm_fields', 'lbm_set_fields',
@@ -423,6 +424,7 @@ class UNet:
             raise LbmError(rc, self.lib.nn_unet_last_error(None).decode())
         self.u = u
         self.loss_buf = torch.zeros(2, dtype=torch.float64, device=self.device)
+        self.norm_buf = torch.zeros(2, dtype=torch.float64, device=self.device)
 
     def _check(self, rc):
         if rc != NN_OK:
@@ -459,6 +461,12 @@ class UNet:
         self._check(self.lib.nn_unet_backward(self.u, ctypes.c_void_p(target.data_ptr()), mp,
                                               ctypes.c_void_p(self.loss_buf.data_ptr())))
         return self.loss_buf
+
+    def clip_grad_norm(self, max_norm):
+        """Scale the gradient to global L2 norm <= max_norm; returns the device buffer
+        {norm before clipping, applied scale}."""
+        self._check(self.lib.nn_unet_clip_grad_norm(self.u, float(max_norm), ctypes.c_void_p(self.norm_buf.data_ptr())))
+        return self.norm_buf
 
     def adam(self, lr, t, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
         self._check(self.lib.nn_unet_adam(self.u, float(lr), float(beta1), float(beta2), float(eps), int(t),

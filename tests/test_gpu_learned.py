@@ -158,6 +158,27 @@ def test_adam_step_matches_reference(lbmib, gpu_net):
     assert np.max(np.abs(theta1 - ref)) <= 1e-6 * max(1.0, np.abs(ref).max())
 
 
+def test_clip_grad_norm_matches_reference(lbmib, net_case):
+    theta, x, tgt, mask = net_case
+    import torch
+    net = lbmib.UNet(B, H, W)
+    net.set_params(theta)
+    net.forward(torch.tensor(x.astype(np.float32), device='cuda'))
+    net.backward(torch.tensor(tgt.astype(np.float32), device='cuda'), torch.tensor(mask.astype(np.float32), device='cuda'))
+    g0 = net.get_grads().astype(np.float64)
+    for bound in (0.5 * np.linalg.norm(g0), 2.0 * np.linalg.norm(g0)):
+        net.backward(torch.tensor(tgt.astype(np.float32), device='cuda'),
+                     torch.tensor(mask.astype(np.float32), device='cuda'))
+        info = net.clip_grad_norm(bound).cpu().numpy()
+        ref, norm = U.clip_grad_norm(g0, bound)
+        g1 = net.get_grads().astype(np.float64)
+        print('norm', info[0], norm, 'scale', info[1], flush=True)
+        assert abs(info[0] - norm) <= 1e-6 * norm
+        assert relL2(g1, ref) <= 1e-6
+    with pytest.raises(lbmib.LbmError):
+        net.clip_grad_norm(0.0)
+
+
 def test_short_fit_reduces_loss(lbmib, net_case):
     import torch
     theta, x, tgt, _ = net_case

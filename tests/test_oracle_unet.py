@@ -94,6 +94,15 @@ def test_adam_first_step_closed_form():
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
 
 
+def test_clip_grad_norm_closed_form():
+    # a 3-4-12 vector has norm 13: clipped to 6.5 it halves; below the bound it is unchanged
+    g = np.array([3.0, -4.0, 12.0])
+    c, n = U.clip_grad_norm(g, 6.5)
+    assert n == 13.0 and np.array_equal(c, g / 2)
+    c, n = U.clip_grad_norm(g, 20.0)
+    assert n == 13.0 and np.array_equal(c, g)
+
+
 def test_bf16_rounding_values():
     x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, 1.0 + 2 ** -7 + 2 ** -8, -3.14159265, 0.0])
     r = U.bf16_round(x)
