@@ -99,6 +99,35 @@ def test_batch_matches_single_grid(lbmib, precision):
     batch.close()
 
 
+def test_batch_mixes_methods_walls_and_bodies(lbmib):
+    """One batch holding the three methods, fixed and turning walls, isothermal and adiabatic
+    walls, an ellipse, a cylinder and a star: each case equals its single-grid run (FP64)."""
+    cases = [
+        wl.cylinder_case(nx=96, ny=48, center=(30.2, 24.3), diameter=12.0, markers=38, method=wl.METHOD_DIBM,
+                         mach=0.1, steps=1),
+        wl.cylinder_case(nx=80, ny=40, center=(24.6, 19.8), diameter=10.0, markers=32, method=wl.METHOD_FODIBM,
+                         mach=0.1, T_wall_ratio=None, omega_star=0.5, steps=1),
+        wl.star_case(48, 0.1, 0.3, 0.1, 30.0, nx=128, ny=64, steps=1),
+        wl.ellipse_case(40, 2.0, 0.4, 0.12, 40.0, None, nx=160, ny=80),
+    ]
+    cases[3].u_wall = wl.rotation_wall_velocity(cases[3].X, cases[3].extra['center'], -0.004)
+    ref = solvers_for(lbmib, cases, lbmib.F64)
+    bat = solvers_for(lbmib, cases, lbmib.F64)
+    batch = lbmib.Batch(bat, autotune=False)
+    for s in ref:
+        s.step(7)
+    batch.step(7)
+    for k, (a, b) in enumerate(zip(ref, bat)):
+        err = state_rel(b.get_state(), a.get_state())
+        la, lb = a.loads(), b.loads()
+        print(f'case {k} ({cases[k].name}, method {cases[k].method}): state rel {err:.2e}, '
+              f'eps_dir {la["eps_dir"]:.4e}/{lb["eps_dir"]:.4e}', flush=True)
+        assert err <= 1e-12
+        for key in ('Cd', 'Cl', 'eps_dir', 'eps_neu', 'eps_iso'):
+            assert abs(la[key] - lb[key]) <= 1e-10 * max(1.0, abs(la[key]))
+    batch.close()
+
+
 @pytest.mark.parametrize('tile', [62, 126, 254])
 def test_batch_tile_widths_agree(lbmib, tile):
     """Every tile width gives the single-grid result (FP64, 6 steps)."""
