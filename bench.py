@@ -178,7 +178,7 @@ def bench_learned(args):
         'value': round(ev['speedup_wall'], 4), 'unit': 'x (cold wall time / warm wall time incl. inference)',
         'n_gpus': 1, 'steps': None, 'warmup': 0, 'ms_per_step': None, 'higher_is_better': True,
         'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64 solver, bf16 network', 'data': 'synthetic',
-        'config': {'workload': f'learned: {args.train_cases} training seeds ({args.shape}), {args.heldout_cases} '
+        'config': {'workload': f'learned: {args.train_cases} steady training cases ({args.shape}), {args.heldout_cases} '
                                f'held-out seeds ({ev["eval_shape"]}), {args.epochs} epochs, 5-level U-Net 32..256 '
                                'channels'},
         'roofline': {'bound': 'mfma', 'kernel': 'U-Net training step (forward + backward + Adam), batch 16',
@@ -234,9 +234,9 @@ def main():
     ap.add_argument('--sweep', choices=('fused', 'threepass'), default='fused')
     ap.add_argument('--workload', choices=('sphere3d', 'batch64', 'learned', 'methods'), default='sphere3d')
     ap.add_argument('--quick', action='store_true', help='methods workload: shorter runs')
-    ap.add_argument('--train-cases', type=int, default=4000)
+    ap.add_argument('--train-cases', type=int, default=2000)
     ap.add_argument('--heldout-cases', type=int, default=512)
-    ap.add_argument('--epochs', type=int, default=160)
+    ap.add_argument('--epochs', type=int, default=240)
     ap.add_argument('--shape', choices=('ellipse', 'star', 'mixed'), default='ellipse',
                     help='learned workload: bodies of the training cases')
     ap.add_argument('--eval-shapes', default=None, help='learned workload: bodies of the held-out cases')
