@@ -77,6 +77,26 @@ def copy_kernel(nbytes):
     print(json.dumps({'copy_bytes': n * 4, 'launches': 3}))
 
 
+def measured_copy_gbs(nbytes=2 << 30, reps=10):
+    """Device-to-device copy bandwidth (bytes read + written per second, GB/s), median of reps
+    copies of nbytes timed with events on the current stream."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device='cuda:0')
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        b.copy_(a)
+        e1.record()
+    torch.cuda.synchronize()
+    ms = sorted(e0.elapsed_time(e1) for e0, e1 in ev)[reps // 2]
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(seconds_hint=20.0):
     """FP64 oracle on a bounded crop: the same sphere (D = 32, 3217 markers) in 96 x 48 x 48."""
     from oracle import ib as oib
@@ -161,6 +181,9 @@ def bench_batch(args):
         'nonfinite_cases': n_bad,
     }
     batch.close()
+    copy_gbs = measured_copy_gbs()
+    out['roofline']['measured_copy_gbs'] = round(copy_gbs, 1)
+    out['roofline']['frac_of_copy'] = round(achieved / copy_gbs, 4)
     print(json.dumps(out))
 
 
@@ -311,6 +334,9 @@ def main():
     solver.close()
     del solver
     torch.cuda.empty_cache()
+    copy_gbs = measured_copy_gbs()
+    out['roofline']['measured_copy_gbs'] = round(copy_gbs, 1)
+    out['roofline']['frac_of_copy'] = round(achieved / copy_gbs, 4)
     if not args.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline()
     print(json.dumps(out))
