@@ -242,9 +242,10 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_lds(const __bf16* __restrict
     const int HW = H * Wd;
     const long long pbeg = (long long)s * split_len;
     const long long pend = pbeg + split_len < P ? pbeg + split_len : P;
-    // staging roles
+    // staging roles: the pixel is the fastest index, so that the lanes of a wavefront store
+    // consecutive pixels of one or two LDS rows (transposed stores free of bank conflicts)
     constexpr int AG = BM / 8;                     // 8-channel groups of dY per pixel
-    const int a_pix = t / AG, a_g = t % AG;        // valid for t < 32 * AG
+    const int a_pix = t % KP, a_g = t / KP;        // valid for t < 32 * AG
     const bool a_on = t < KP * AG;
     float bsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     f32x4 acc[2][2];
@@ -267,7 +268,7 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_lds(const __bf16* __restrict
         for (int r = 0; r < (BN * KP / 8 + 255) / 256; ++r) {
             const int v_ = t + 256 * r;
             if (v_ < BN * KP / 8) {
-                const int pix = v_ / (BN / 8), g = v_ % (BN / 8);
+                const int pix = v_ % KP, g = v_ / KP;
                 const int k = k0 + 8 * g;
                 const long long p = q + pix;
                 bf16x8 v = zero;
