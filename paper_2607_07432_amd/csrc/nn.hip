@@ -114,25 +114,30 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
 }
 
 // Convolution forward (3x3) with the input staged through LDS. A workgroup of 4 wavefronts owns
-// COB output channels x 64 pixels, the pixels being a TH x TW block of one image (TW = min(64, W),
-// TH = 64 / TW, rows beyond the image masked). Per chunk of 32 input channels it stages the
+// COB output channels x CONV_NPX pixels, the pixels being a TH x TW block of one image
+// (TW = min(64, W), TH = CONV_NPX / TW, rows beyond the image masked). Per chunk of 32 input channels it stages the
 // (TH + 2) x (TW + 2) input block with its one-pixel halo (zero outside the image) as 16-byte
 // vectors into LDS ([pixel][channel], padded), then runs the nine taps from there: the B operand
 // of tap (dy, dx) for output pixel (ty, tx) is the staged pixel (ty + dy + 1, tx + dx + 1), so
 // every input value is read from memory once per chunk instead of once per tap. The A operand
-// (weights, shared by all workgroups) is read from global memory as in k_conv_fwd. Wavefront w
-// computes 32 channels x (64 / WN) pixels with WM = COB / 32 wavefronts along the channels.
+// (weights) is read from global memory as in k_conv_fwd when COB = 64 (two wavefronts share each
+// weight row); with COB = 32 all four wavefronts need the same weights, so the chunk's weights of
+// all nine taps are staged in LDS too ([tap][channel][32 + 8]) and read from there. Wavefront w
+// computes 32 channels x (CONV_NPX / WN) pixels with WM = COB / 32 wavefronts along the channels.
 // Requires cin % 32 == 0, cout % COB == 0, xstride % 8 == 0, ystride, yoff % 4 == 0.
+constexpr int CONV_NPX = 128;                       // output pixels per workgroup
 template <int COB>
 __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__ X, int cin, int xstride,
                                                       const __bf16* __restrict__ Wt, const float* __restrict__ bias,
                                                       int cout, int H, int Wd, int tw, int relu,
                                                       __bf16* __restrict__ Y, int ystride, int yoff) {
     constexpr int CK = 32, LDP = CK + 8;
-    constexpr int MAXP = 3 * 66;                    // largest staged block: TH = 1, TW = 64
-    constexpr int WM = COB / 32, WN = 4 / WM, TNW = 4 / WN;
+    constexpr int MAXP = (CONV_NPX / 64 + 2) * 66;  // largest staged block: TW = 64
+    constexpr int WM = COB / 32, WN = 4 / WM, TNW = CONV_NPX / (16 * WN);
+    constexpr bool WST = COB == 32;                 // weights staged in LDS
     __shared__ __bf16 patch[MAXP * LDP];
-    const int th = 64 / tw;
+    __shared__ __bf16 wst[WST ? 9 * COB * LDP : 1];
+    const int th = CONV_NPX / tw;
     const int pw = tw + 2, np = (th + 2) * pw;
     const int co_tiles = cout / COB;
     const int bx_tiles = Wd / tw, by_tiles = (H + th - 1) / th;
@@ -153,7 +158,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__
     int tyj[TNW], txj[TNW];
 #pragma unroll
     for (int j = 0; j < TNW; ++j) {
-        const int q = wn * (64 / WN) + j * 16 + lane % 16;   // pixel of the block
+        const int q = wn * (CONV_NPX / WN) + j * 16 + lane % 16;   // pixel of the block
         tyj[j] = q / tw;
         txj[j] = q % tw;
     }
@@ -175,6 +180,14 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__
                 val = *reinterpret_cast<const bf16x8*>(X + (img + (long long)y * Wd + x) * xstride + ci0 + 8 * g);
             *reinterpret_cast<bf16x8*>(patch + pix * LDP + 8 * g) = val;
         }
+        if constexpr (WST) {
+            for (int v = t; v < 9 * COB * (CK / 8); v += 256) {
+                const int g = v % (CK / 8), row = v / (CK / 8);      // row = tap * COB + channel
+                const int tap = row / COB, co = row % COB;
+                *reinterpret_cast<bf16x8*>(wst + row * LDP + 8 * g) = *reinterpret_cast<const bf16x8*>(
+                    Wt + (long long)(cot * COB + co) * K + (long long)tap * cin + ci0 + 8 * g);
+            }
+        }
         __syncthreads();
 #pragma unroll 3
         for (int tap = 0; tap < 9; ++tap) {
@@ -182,8 +195,12 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__
             const long long kk = (long long)tap * cin + ci0 + kg;
             bf16x8 a[2], bv[TNW];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                a[i] = *reinterpret_cast<const bf16x8*>(Wt + (long long)(co_w + i * 16 + lane % 16) * K + kk);
+            for (int i = 0; i < 2; ++i) {
+                if constexpr (WST)
+                    a[i] = *reinterpret_cast<const bf16x8*>(wst + (tap * COB + wm * 32 + i * 16 + lane % 16) * LDP + kg);
+                else
+                    a[i] = *reinterpret_cast<const bf16x8*>(Wt + (long long)(co_w + i * 16 + lane % 16) * K + kk);
+            }
 #pragma unroll
             for (int j = 0; j < TNW; ++j)
                 bv[j] = *reinterpret_cast<const bf16x8*>(patch + ((tyj[j] + dy) * pw + txj[j] + dx) * LDP + kg);
@@ -847,9 +864,9 @@ hipError_t conv_fwd(nn_unet* u, const Layer& ly, const __bf16* X, int xstride, c
     const long long P = (long long)B * H * W;
     // 3x3 layers with 32-channel multiples and power-of-two widths: input staged through LDS
     if (ly.taps == 9 && ly.cin % 32 == 0 && ly.cout % 32 == 0 && xstride % 8 == 0 && ystride % 4 == 0 &&
-        yoff % 4 == 0 && W >= 1 && (W & (W - 1)) == 0) {
+        yoff % 4 == 0 && W >= 8 && (W & (W - 1)) == 0) {      // W >= 8: the staged block fits MAXP
         const int tw = W < 64 ? W : 64;
-        const int th = 64 / tw;
+        const int th = CONV_NPX / tw;
         const long long nblk = (long long)B * ((H + th - 1) / th) * (W / tw);
         if (ly.cout % 64 == 0)
             hipLaunchKernelGGL((k_conv_fwd_lds<64>), dim3((unsigned)(nblk * (ly.cout / 64))), dim3(256), 0, u->stream,
