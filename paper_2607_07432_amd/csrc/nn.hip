@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
 }
 
 // Convolution forward (3x3) with the input staged through LDS. A workgroup of 4 wavefronts owns
-// COB output channels x CONV_NPX pixels, the pixels being a TH x TW block of one image
+// COB output channels x CONV_NPX (64 or 128) pixels, the pixels being a TH x TW block of one image
 // (TW = min(64, W), TH = CONV_NPX / TW, rows beyond the image masked). Per chunk of 32 input channels it stages the
 // (TH + 2) x (TW + 2) input block with its one-pixel halo (zero outside the image) as 16-byte
 // vectors into LDS ([pixel][channel], padded), then runs the nine taps from there: the B operand
@@ -125,8 +125,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
 // all nine taps are staged in LDS too ([tap][channel][32 + 8]) and read from there. Wavefront w
 // computes 32 channels x (CONV_NPX / WN) pixels with WM = COB / 32 wavefronts along the channels.
 // Requires cin % 32 == 0, cout % COB == 0, xstride % 8 == 0, ystride, yoff % 4 == 0.
-constexpr int CONV_NPX = 128;                       // output pixels per workgroup
-template <int COB>
+template <int COB, int CONV_NPX>
 __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__ X, int cin, int xstride,
                                                       const __bf16* __restrict__ Wt, const float* __restrict__ bias,
                                                       int cout, int H, int Wd, int tw, int relu,
@@ -866,14 +865,24 @@ hipError_t conv_fwd(nn_unet* u, const Layer& ly, const __bf16* X, int xstride, c
     if (ly.taps == 9 && ly.cin % 32 == 0 && ly.cout % 32 == 0 && xstride % 8 == 0 && ystride % 4 == 0 &&
         yoff % 4 == 0 && W >= 8 && (W & (W - 1)) == 0) {      // W >= 8: the staged block fits MAXP
         const int tw = W < 64 ? W : 64;
-        const int th = CONV_NPX / tw;
-        const long long nblk = (long long)B * ((H + th - 1) / th) * (W / tw);
-        if (ly.cout % 64 == 0)
-            hipLaunchKernelGGL((k_conv_fwd_lds<64>), dim3((unsigned)(nblk * (ly.cout / 64))), dim3(256), 0, u->stream,
-                               X, ly.cin, xstride, Wt, bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
+        const int cob = ly.cout % 64 == 0 ? 64 : 32;
+        // 128 pixels per workgroup unless that leaves fewer than two workgroups per CU
+        const long long blk128 = (long long)B * ((H + 128 / tw - 1) / (128 / tw)) * (W / tw) * (ly.cout / cob);
+        const int npx = blk128 >= 512 ? 128 : 64;
+        const int th = npx / tw;
+        const unsigned nblk = (unsigned)((long long)B * ((H + th - 1) / th) * (W / tw) * (ly.cout / cob));
+        if (cob == 64 && npx == 128)
+            hipLaunchKernelGGL((k_conv_fwd_lds<64, 128>), dim3(nblk), dim3(256), 0, u->stream, X, ly.cin, xstride, Wt,
+                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
+        else if (cob == 64)
+            hipLaunchKernelGGL((k_conv_fwd_lds<64, 64>), dim3(nblk), dim3(256), 0, u->stream, X, ly.cin, xstride, Wt,
+                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
+        else if (npx == 128)
+            hipLaunchKernelGGL((k_conv_fwd_lds<32, 128>), dim3(nblk), dim3(256), 0, u->stream, X, ly.cin, xstride, Wt,
+                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
         else
-            hipLaunchKernelGGL((k_conv_fwd_lds<32>), dim3((unsigned)(nblk * (ly.cout / 32))), dim3(256), 0, u->stream,
-                               X, ly.cin, xstride, Wt, bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
+            hipLaunchKernelGGL((k_conv_fwd_lds<32, 64>), dim3(nblk), dim3(256), 0, u->stream, X, ly.cin, xstride, Wt,
+                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
         return hipGetLastError();
     }
     constexpr int TM = 2, TN = 4;
