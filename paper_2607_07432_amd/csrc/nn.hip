@@ -531,10 +531,20 @@ __global__ void __launch_bounds__(256) k_head_wgrad(const __bf16* __restrict__ A
 }
 
 // Column sums of a [rows][n] FP32 array in fixed order: out[i] = sum_r part[r][i].
-__global__ void k_colsum(const float* __restrict__ part, int rows, int n, float* __restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    out[i] = strided_sum8(part, rows, n, i);
+// One workgroup per column: thread t adds rows t, t + 256, ... in order, then a fixed-order
+// tree in LDS (the result does not depend on the launch).
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ part, int rows, int n, float* __restrict__ out) {
+    __shared__ float red[256];
+    const int i = blockIdx.x;
+    float acc = 0.f;
+    for (int r = threadIdx.x; r < rows; r += 256) acc += part[(long long)r * n + i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = red[0];
 }
 
 // Masked mean squared error over P pixels and 4 planes (mask NULL: all ones).
@@ -920,7 +930,7 @@ hipError_t conv_wgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, co
                            H, W, P, (int)split_len, (int)nsplit, u->split, u->small);
     hipLaunchKernelGGL(k_sum_splits, dim3(blocks(wsz)), dim3(256), 0, u->stream, (const float*)u->split, (int)nsplit, wsz,
                        u->grad + ly.w_off);
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(ly.cout)), dim3(256), 0, u->stream, (const float*)u->small, (int)nsplit,
+    hipLaunchKernelGGL(k_colsum, dim3(ly.cout), dim3(256), 0, u->stream, (const float*)u->small, (int)nsplit,
                        ly.cout, u->grad + ly.b_off);
     return hipGetLastError();
 }
@@ -1011,7 +1021,7 @@ int backward(nn_unet* u, const float* d_tgt, const float* d_mask, double* d_loss
                        (const float*)u->dout, P0, u->dec_b[0].g);
     hipLaunchKernelGGL(k_head_wgrad, dim3(nh), dim3(256), 0, u->stream, (const __bf16*)u->dec_b[0].a,
                        (const float*)u->dout, P0, u->small);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, u->stream, (const float*)u->small, nh, HEAD_NP,
+    hipLaunchKernelGGL(k_colsum, dim3(HEAD_NP), dim3(256), 0, u->stream, (const float*)u->small, nh, HEAD_NP,
                        u->grad + hd.w_off);
     NCHK(u, hipGetLastError());
     // decoder, top level first
