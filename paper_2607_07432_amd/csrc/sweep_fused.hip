@@ -89,6 +89,22 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     constexpr int D = L::D;
     const FusedK<C>& g = a;
     const long long N = g.N;
+    // Every state and forcing array lives in device memory: accessed through pointers typed in
+    // the global address space, also when they were read from a device table.
+    using GS = __attribute__((address_space(1))) S;
+    using GD = __attribute__((address_space(1))) double;
+    using GI = __attribute__((address_space(1))) const int;
+    GS* const Af = (GS*)A.f;
+    GS* const Ae = (GS*)A.e;
+    GS* const Ah = (GS*)A.h2;
+    GS* const Bf = (GS*)B.f;
+    GS* const Be = (GS*)B.e;
+    GS* const Bh = (GS*)B.h2;
+    GI* const rowmap = (GI*)a.rows.rowmap;
+    GD* const rfib = (GD*)a.rows.fib;
+    GD* const rfE = (GD*)a.rows.fE;
+    const GD* const rh2off = (const GD*)a.rows.h2off;
+    GD* const rh2out = (GD*)a.rows.h2off_out;
     const int nm = D == 3 ? g.nz : g.ny;               // length of the marching axis
     const int t = threadIdx.x;
 
@@ -147,17 +163,17 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     auto load_plane = [&](int q) {
         const long long n = gnode(x0 - 1 + jx1, y0 - G::OY + jy1, q);
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) nxt.f[i] = A.f[i * N + n];
-        nxt.e = A.e[n];
-        nxt.h[0] = A.h2[n];
-        nxt.h[1] = D == 3 ? A.h2[N + n] : S(0);
-        nxt.r = a.rows.rowmap[n];
+        for (int i = 0; i < L::Q; ++i) nxt.f[i] = Af[i * N + n];
+        nxt.e = Ae[n];
+        nxt.h[0] = Ah[n];
+        nxt.h[1] = D == 3 ? Ah[N + n] : S(0);
+        nxt.r = rowmap[n];
         if (ring) {
             const long long m = gnode(x0 - 2 + rjx, y0 - 2 * G::OY + rjy, q);
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) rf[i] = A.f[i * N + m];
-            re = A.e[m];
-            rr = a.rows.rowmap[m];
+            for (int i = 0; i < L::Q; ++i) rf[i] = Af[i * N + m];
+            re = Ae[m];
+            rr = rowmap[m];
         }
     };
     auto shift_planes = [&]() { cur = nxt; };
@@ -182,7 +198,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         sm.mac[sl][0][k] = rho;
 #pragma unroll
         for (int b = 0; b < D; ++b) {
-            const C fib = r >= 0 ? C(a.rows.fib[(long long)b * a.rows.nrows + r]) : C(0);
+            const C fib = r >= 0 ? C(rfib[(long long)b * a.rows.nrows + r]) : C(0);
             sm.mac[sl][1 + b][k] = (j[b] + C(0.5) * fib) * ir;
         }
         sm.mac[sl][1 + D][k] = T;
@@ -261,9 +277,9 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
             C fib[3] = {0, 0, 0}, off[3] = {0, 0, 0};
             if (r >= 0) {
 #pragma unroll
-                for (int b = 0; b < D; ++b) fib[b] = C(a.rows.fib[(long long)b * nr + r]);
+                for (int b = 0; b < D; ++b) fib[b] = C(rfib[(long long)b * nr + r]);
 #pragma unroll
-                for (int kk = 0; kk < L::NOFF; ++kk) off[kk] = C(a.rows.h2off[(long long)kk * nr + r]);
+                for (int kk = 0; kk < L::NOFF; ++kk) off[kk] = C(rh2off[(long long)kk * nr + r]);
             }
             H2[0][1] = H2[1][0] = off[0];
             if (D == 3) {
@@ -285,18 +301,18 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
                               (D == 2 || yu < g.ny);
             if (tile) {
                 if (r >= 0) {
-                    a.rows.h2off_out[r] = H2n[0][1];
+                    rh2out[r] = H2n[0][1];
                     if (D == 3) {
-                        a.rows.h2off_out[(long long)nr + r] = H2n[0][2];
-                        a.rows.h2off_out[2LL * nr + r] = H2n[1][2];
+                        rh2out[(long long)nr + r] = H2n[0][2];
+                        rh2out[2LL * nr + r] = H2n[1][2];
                     }
                 }
                 int copies = 1;
                 bool write = true;
                 if (g.bc_x == 1) {
                     if (xu < 2) {
-                        B.h2[n] = S(0);
-                        if (D == 3) B.h2[N + n] = S(0);
+                        Bh[n] = S(0);
+                        if (D == 3) Bh[N + n] = S(0);
                         write = false;
                     } else if (xu >= g.nx - 2) {
                         write = false;
@@ -306,8 +322,8 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
                 }
                 if (write)
                     for (int c = 0; c < copies; ++c) {
-                        B.h2[n + c] = S(H2n[0][0]);
-                        if (D == 3) B.h2[N + n + c] = S(H2n[1][1]);
+                        Bh[n + c] = S(H2n[0][0]);
+                        if (D == 3) Bh[N + n + c] = S(H2n[1][1]);
                     }
             }
         }
@@ -394,7 +410,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     // energy and row of the own node for its output one plane later (its forcing is prefetched)
     S ekeep = cur.e;
     int rkeep = cur.r;
-    C fEkeep = rkeep >= 0 ? C(a.rows.fE[rkeep]) : C(0);
+    C fEkeep = rkeep >= 0 ? C(rfE[rkeep]) : C(0);
     shift_planes();                                 // cur: plane z0 + 1
     __syncthreads();
     C fm_prev = 0;                                  // energy flux through the p - 1/2 face
@@ -422,8 +438,8 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         if (g.bc_x == 1) {
             if (xo < 2) {
 #pragma unroll
-                for (int i = 0; i < L::Q; ++i) B.f[i * N + n] = S(a.fdev[i]);
-                B.e[n] = S(0);
+                for (int i = 0; i < L::Q; ++i) Bf[i * N + n] = S(a.fdev[i]);
+                Be[n] = S(0);
                 return;
             }
             if (xo >= g.nx - 2) return;
@@ -432,8 +448,8 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         const int copies = (g.bc_x == 1 && xo == g.nx - 3) ? 3 : 1;
         for (int c = 0; c < copies; ++c) {
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) B.f[i * N + n + c] = S(pf[i]);
-            B.e[n + c] = S(enew);
+            for (int i = 0; i < L::Q; ++i) Bf[i * N + n + c] = S(pf[i]);
+            Be[n + c] = S(enew);
         }
     };
 
@@ -448,7 +464,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         const C fEout = fEkeep;
         ekeep = cur.e;                              // plane p + 1
         rkeep = cur.r;
-        fEkeep = rkeep >= 0 ? C(a.rows.fE[rkeep]) : C(0);
+        fEkeep = rkeep >= 0 ? C(rfE[rkeep]) : C(0);
         shift_planes();                             // cur: plane p + 2
         if (p + 1 < z1) load_plane(p + 3);
 
@@ -524,8 +540,12 @@ __global__ void __launch_bounds__(TX + 2) k_fused_batch(const CaseDesc<S>* __res
         const int x0 = (local % cd.tiles_x) * TX;
         const int z0 = chunk * cd.chunk;
         const int z1 = min(z0 + cd.chunk, cd.k[0].ny);
+        // the case's arguments in registers for the whole item
+        const FusedK<S> ka = cd.k[cur];
+        const StateP<S> A = cd.st[cur], B = cd.st[cur ^ 1];
+        const bool small = cd.small != 0;
         __syncthreads();                              // the previous item's LDS reads are done
-        fused_tile<L, S, S, TX, 1, 2>(cd.k[cur], cd.st[cur], cd.st[cur ^ 1], x0, 0, z0, z1, cd.small != 0, sm);
+        fused_tile<L, S, S, TX, 1, 2>(ka, A, B, x0, 0, z0, z1, small, sm);
     }
 }
 
