@@ -200,6 +200,32 @@ def test_short_fit_reduces_loss(lbmib, net_case):
     assert np.isfinite(losses).all() and losses[-1] < 0.1 * losses[0]
 
 
+def test_failed_warm_start_is_flagged_and_cold_start_converges(lbmib):
+    """A warm start from a prediction holding NaN (forced from the host) leaves a non-finite
+    state; the batched march flags it instead of converging, and the cold start of the same case
+    reaches the tolerance. The other case of the batch is not affected."""
+    import torch
+    from paper_2607_07432_amd import learned
+    cases = [small_case(21), small_case(22)]
+    warm = [lbmib.Solver.from_case(c, precision=lbmib.F64) for c in cases]
+    good = torch.zeros((64, 128, 4), dtype=torch.float32, device='cuda')
+    good[..., 1] = 1.0                                                          # the free stream
+    bad = good.clone()
+    bad[30, 40, 1] = float('nan')
+    warm[0].warm_start(bad)
+    warm[1].warm_start(good)
+    steps, flags, _, _ = learned.run_to_steady(warm, 1e-5, 20000, 250)
+    print('warm', steps, flags, flush=True)
+    assert flags[0] and steps[0] is None
+    assert not flags[1] and steps[1] is not None
+    cold = [lbmib.Solver.from_case(cases[0], precision=lbmib.F64)]
+    steps_c, flags_c, _, _ = learned.run_to_steady(cold, 1e-5, 20000, 250)
+    print('cold', steps_c, flags_c, flush=True)
+    assert not flags_c[0] and steps_c[0] is not None
+    for s in warm + cold:
+        s.close()
+
+
 def test_trained_network_shortens_time_to_steady(lbmib):
     """Train on the steady states the solver reaches from 200 seeds (128 x 64, ellipses of 32
     markers), then march 8 held-out cases to r < 1e-7 from the warm and from the cold start."""
