@@ -21,4 +21,8 @@ Modules
 
 Every floating-point value is numpy float64. No blocking, fusion or reordering
 beyond what the paper's definitions state.
+
+Parity unpinned by the paper: a^C and the time derivative in Eq. (A.9) (lbm), the absolute
+loads (loads), and the network and warm-start helpers (unet, warmstart), which the paper does
+not contain; each is pinned by definitions, closed forms or physics tests instead.
 """

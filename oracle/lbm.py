@@ -18,6 +18,11 @@ Follows Sec. 2.2 and Appendix A of the paper:
 
 Lattice units: dx = dt = 1, temperatures in units of T_ref (theta = T), R = c_s^2 = 1/3.
 
+Parity unpinned by the paper (pinned only by physics tests and oracle-GPU agreement): the
+lattice correction a^C inside a^F, which Eq. (A.9) defines only by reference (read here as the
+missing diagonal third-order equilibrium moment, -delta_ab d_a(rho u_a^3)), and the time
+derivative d/dt[rho (1 - theta)] of Eq. (A.9), evaluated from the first-order balance laws.
+
 Arrays: a scalar field has the grid shape (ny, nx) in 2D or (nz, ny, nx) in 3D
 (x fastest); populations are (Q, *grid); vectors (D, *grid); tensors (D, D, *grid).
 Neighbour access wraps periodically in every direction; the inflow/outflow
