@@ -270,24 +270,23 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_lds(const __bf16* __restrict
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero = {};
-    for (long long q = pbeg; q < pend; q += KP) {
+    // Software pipeline: the global loads of the next slice go into registers before the MFMA
+    // of the current one, and are stored (transposed) into LDS after the barrier that ends it.
+    constexpr int BR = (BN * KP / 8 + 255) / 256;   // X^ vectors per thread and slice
+    bf16x8 va = zero, vb[BR];
+    auto load = [&](long long q) {
         if (a_on) {
             const long long p = q + a_pix;
-            const bf16x8 v = p < pend ? *reinterpret_cast<const bf16x8*>(dY + p * dys + co0 + 8 * a_g) : zero;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                As[8 * a_g + e][a_pix] = v[e];
-                bsum[e] += (float)v[e];
-            }
+            va = p < pend ? *reinterpret_cast<const bf16x8*>(dY + p * dys + co0 + 8 * a_g) : zero;
         }
 #pragma unroll
-        for (int r = 0; r < (BN * KP / 8 + 255) / 256; ++r) {
+        for (int r = 0; r < BR; ++r) {
             const int v_ = t + 256 * r;
+            vb[r] = zero;
             if (v_ < BN * KP / 8) {
                 const int pix = v_ % KP, g = v_ / KP;
                 const int k = k0 + 8 * g;
                 const long long p = q + pix;
-                bf16x8 v = zero;
                 if (k < K && p < pend) {
                     const int tap = k / cin, ci = k - tap * cin;
                     const int dy = taps == 9 ? tap / 3 - 1 : 0, dx = taps == 9 ? tap % 3 - 1 : 0;
@@ -295,13 +294,34 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_lds(const __bf16* __restrict
                     const int rr = (int)(p - n * HW);
                     const int y = rr / Wd + dy, x = rr % Wd + dx;
                     if (y >= 0 && y < H && x >= 0 && x < Wd)
-                        v = *reinterpret_cast<const bf16x8*>(X + (n * HW + (long long)y * Wd + x) * xs + ci);
+                        vb[r] = *reinterpret_cast<const bf16x8*>(X + (n * HW + (long long)y * Wd + x) * xs + ci);
                 }
-#pragma unroll
-                for (int e = 0; e < 8; ++e) Bs[8 * g + e][pix] = v[e];
             }
         }
+    };
+    auto store = [&]() {
+        if (a_on) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                As[8 * a_g + e][a_pix] = va[e];
+                bsum[e] += (float)va[e];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            const int v_ = t + 256 * r;
+            if (v_ < BN * KP / 8) {
+                const int pix = v_ % KP, g = v_ / KP;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) Bs[8 * g + e][pix] = vb[r][e];
+            }
+        }
+    };
+    if (pbeg < pend) load(pbeg);
+    for (long long q = pbeg; q < pend; q += KP) {
+        store();
         __syncthreads();
+        if (q + KP < pend) load(q + KP);
         bf16x8 a[2], bb[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + i * 16 + lane % 16][8 * (lane / 16)]);
