@@ -8,7 +8,10 @@ Sec. 3.4 (Dirichlet velocity, Neumann heat flux, isothermal temperature), the lo
 time of a step split into the marker kernel (interpolation, reconstruction, forces), the
 spreading and the grid sweep, i.e. the cost the reconstruction adds (Sec. 3.3).
 
-    python -m paper_2607_07432_amd.methods [--quick]
+    python -m paper_2607_07432_amd.methods [--quick] [--couette]
+
+With --couette it instead runs circular Couette flow between a turning inner and a fixed outer
+cylinder, where the steady profile is known, at growing resolution (couette_convergence).
 
 The flow configurations are subsonic, on a uniform grid, with inflow/outflow in x; the paper's
 error tables use a supersonic cylinder on refined meshes, which this solver does not model
@@ -105,6 +108,72 @@ def compare(quick=False, log=None, only=None):
     return res
 
 
+def couette_errors(case, rho, u):
+    """Errors of u_theta against the analytic circular Couette profile, and where the flow puts
+    the walls.
+
+    Relative L2 and maximum error over the nodes strictly inside the gap and over the core
+    r1 + 2 <= r <= r2 - 2. Effective wall radii: u_theta = a r + b / r (the general steady
+    solution) is fitted over r1 + 1.5 < r < r2 - 1.5, and solved for the radius where it meets the
+    inner wall's rigid rotation (omega r) and where it vanishes; dr_in = r_in_eff - r1 and
+    dr_out = r_out_eff - r2 are positive outward."""
+    ny, nx = rho.shape
+    cx, cy = case.extra['center']
+    r1, r2, U = case.extra['r1'], case.extra['r2'], case.extra['speed']
+    ys, xs = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    dx, dy = xs - cx, ys - cy
+    r = np.hypot(dx, dy)
+    ut = (-u[0] * dy + u[1] * dx) / np.maximum(r, 1e-300)
+    ex = wl.couette_profile(case, np.maximum(r, 1e-300))
+    out = {}
+    for name, m in (('gap', (r > r1) & (r < r2)), ('core', (r >= r1 + 2) & (r <= r2 - 2))):
+        d = ut[m] - ex[m]
+        out[f'l2_{name}'] = float(np.sqrt((d * d).sum() / (ex[m] ** 2).sum()))
+        out[f'max_{name}'] = float(np.abs(d).max() / U)
+    m = (r > r1 + 1.5) & (r < r2 - 1.5)
+    (a, b), *_ = np.linalg.lstsq(np.stack([r[m], 1.0 / r[m]], axis=1), ut[m], rcond=None)
+    om = U / r1
+    out['dr_in'] = float(np.sqrt(b / (om - a)) - r1) if om > a and b > 0 else float('nan')
+    out['dr_out'] = float(np.sqrt(-b / a) - r2) if a < 0 and b > 0 else float('nan')
+    return out
+
+
+def couette_convergence(scales=(1, 2, 3, 4), log=None, tol=1e-12, check=2000, methods=METHODS):
+    """Circular Couette flow (FP64) for the methods at growing resolution: u_theta against
+    A r + B / r, and the effective wall radii beside the mean d_BV of each wall (zero for DIBM).
+    The march stops when the per-step velocity change (residual with unit velocity scale) is
+    below tol or after 40 viscous times of the gap."""
+    res = {}
+    for mname, m in methods:
+        rows = []
+        for sc in scales:
+            case = wl.taylor_couette_case(sc, method=m)
+            gap = case.extra['r2'] - case.extra['r1']
+            max_steps = int(40 * gap * gap / case.mu / check + 1) * check
+            s = lbmib.Solver.from_case(case, precision=64)
+            steps, r = 0, float('nan')
+            while steps < max_steps:
+                s.step(check)
+                steps += check
+                r = s.residual()
+                if not np.isfinite(r) or r < tol:
+                    break
+            rho, u, T, _ = s.fields()
+            dbv = s.geometry()['dbv']
+            inner = case.extra['n_inner']
+            e = couette_errors(case, rho, u)
+            e.update(scale=sc, nodes=case.n_nodes, steps=steps, residual=r, T_max_dev=float(np.abs(T - 1.0).max()),
+                     dbv_in=float(dbv[:inner].mean()), dbv_out=float(dbv[inner:].mean()))
+            rows.append(e)
+            s.close()
+            if log:
+                log(f'couette {mname} scale {sc}: ' + ', '.join(f'{k} {v:.4g}' for k, v in e.items()))
+        for a, b in zip(rows, rows[1:]):
+            b['order_l2_gap'] = float(np.log(a['l2_gap'] / b['l2_gap']) / np.log(b['scale'] / a['scale']))
+        res[mname] = rows
+    return res
+
+
 def reduction(res, case_idx, key, better='FODIBM-R', base='FODIBM'):
     """Relative change (%) of an error from the base method to the better one."""
     m = res[case_idx]['methods']
@@ -116,9 +185,10 @@ def reduction(res, case_idx, key, better='FODIBM-R', base='FODIBM'):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument('--quick', action='store_true')
+    ap.add_argument('--couette', action='store_true', help='circular Couette convergence instead of the bodies')
     args = ap.parse_args(argv)
     log = lambda msg: print(f'[methods] {msg}', file=sys.stderr, flush=True)
-    res = compare(args.quick, log)
+    res = couette_convergence((1, 2) if args.quick else (1, 2, 3, 4), log) if args.couette else compare(args.quick, log)
     print(json.dumps(res))
     return res
 

@@ -193,6 +193,38 @@ def sphere_case(nx=384, ny=192, nz=192, diameter=32.0, center=None, mach=0.3, re
                 extra={'omega_star': omega_star}, **mk)
 
 
+def taylor_couette_case(scale=1, method=METHOD_FODIBM_R, speed=0.04, nu=0.048, r_in=8.0, r_out=20.0):
+    """Circular Couette flow between an inner cylinder of radius r_in*scale turning at surface
+    speed `speed` and a fixed outer cylinder of radius r_out*scale (fluid in the gap), both walls
+    isothermal at T_inf = 1, periodic box at rest, no free stream. Markers one per unit of arc;
+    inner normals point outward, outer normals inward (into the fluid). The steady solution is
+    u_theta = A r + B / r with u_theta(r1) = speed, u_theta(r2) = 0."""
+    r1, r2 = r_in * scale, r_out * scale
+    n = int(2 * math.ceil(r2 + 6.0))
+    c = (n / 2.0 + 0.31, n / 2.0 - 0.23)
+    m1, m2 = int(round(2 * math.pi * r1)), int(round(2 * math.pi * r2))
+    X1, n1 = cylinder_markers(c, r1, m1)
+    X2, n2o = cylinder_markers(c, r2, m2)
+    X = np.concatenate([X1, X2])
+    nrm = np.concatenate([n1, -n2o])
+    mk = _markers_common(X, nrm, T_DIRICHLET, 1.0)
+    mk['u_wall'] = np.concatenate([rotation_wall_velocity(X1, c, speed / r1), np.zeros_like(X2)])
+    gamma = GAMMA
+    lam = nu * (R_GAS * gamma / (gamma - 1.0)) / PRANDTL
+    case = Case(name='taylor_couette', dim=2, dims=(n, n), mu=nu, lam=lam, u_inf=(0.0, 0.0), T_inf=1.0,
+                bc='periodic', method=method, ref_len=2.0 * r1, ref_area=2.0 * r1, surface=2 * math.pi * r1,
+                T_wall=1.0, steps=1, extra=dict(center=c, r1=r1, r2=r2, speed=speed, n_inner=m1), **mk)
+    return case
+
+
+def couette_profile(case, r):
+    """Analytic u_theta(r) of taylor_couette_case."""
+    r1, r2, U = case.extra['r1'], case.extra['r2'], case.extra['speed']
+    A = -U * r1 / (r2 * r2 - r1 * r1)
+    B = U * r1 * r2 * r2 / (r2 * r2 - r1 * r1)
+    return A * r + B / r
+
+
 def config1(**kw):
     """200 x 100 D2Q9 cylinder D = 20 at (60, 50), 63 markers, Ma 0.2, Re 40, T_w = 1.2 T_inf."""
     return cylinder_case(**kw)
