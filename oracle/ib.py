@@ -59,8 +59,14 @@ def kernel_1d(kind, r):
 
 
 def linear_index(nodes, dims):
-    """x + nx (y + ny z) for integer node coordinates (n, D)."""
+    """x + nx (y + ny z) for integer node coordinates (n, D).
+
+    The map does not wrap: a stencil that leaves the grid is refused (ValueError), as the
+    library refuses markers within 3 cells of an edge."""
     nodes = np.asarray(nodes, dtype=np.int64)
+    hi = np.asarray(dims, dtype=np.int64)[:nodes.shape[1]]
+    if nodes.size and (np.any(nodes < 0) or np.any(nodes >= hi)):
+        raise ValueError('marker stencil leaves the grid')
     lin = nodes[:, -1].copy()
     for a in range(nodes.shape[1] - 2, -1, -1):
         lin = lin * dims[a] + nodes[:, a]

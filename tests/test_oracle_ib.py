@@ -298,3 +298,14 @@ def test_interpolating_a_constant_and_X_star():
     gd, _ = _ring_geometry(ib.DIBM)
     # DIBM: the effective boundary is the marker up to the kernel's first moment
     assert np.abs(gd.Xstar - X).max() < 0.0211 * 1.000001
+
+
+@pytest.mark.parametrize('where', ['low_x', 'high_y', 'projection'])
+def test_stencil_leaving_the_grid_is_refused(where):
+    # the node numbering does not wrap, so a support or projection stencil outside the grid must
+    # not alias onto other nodes
+    X = {'low_x': [[0.7, 10.3]], 'high_y': [[10.2, 18.6]], 'projection': [[10.3, 17.7]]}[where]
+    n = [[0.0, 1.0]] if where == 'projection' else [[1.0, 0.0]]
+    with pytest.raises(ValueError):
+        ib.build_geometry((20, 20), np.array(X), np.array(n), ib.FODIBM_R)
+    ib.build_geometry((20, 20), np.array([[10.2, 10.3]]), np.array([[1.0, 0.0]]), ib.FODIBM_R)
