@@ -351,8 +351,13 @@ def state_from_fields(lat, prm, rho, u, T):
 def apply_closure(lat, prm, st):
     """Inflow/outflow closure along x (reading of the paper's inlet/outlet set-up).
 
-    Columns x = 0, 1 are reset to the free-stream equilibrium (f, rho E, history);
-    columns x = nx-2, nx-1 copy column nx-3 (zero gradient). y and z stay periodic.
+    Columns x = 0, 1 are reset to the free-stream equilibrium (f, rho E, history). Columns
+    x = nx-2, nx-1 take column nx-3 with its populations and total energy multiplied by
+    rho_inf / rho_{nx-3}: the density there is the free-stream one, while u and T (and the
+    history terms, copied as they are) have zero gradient. The paper's far field is
+    characteristic and prescribes the free-stream state, which fixes the mean density; a plain
+    copy leaves it free, and a body in the stream then makes the whole field drift slowly
+    without reaching a steady state. y and z stay periodic.
     """
     if prm.bc != 'inflow_outflow':
         return st
@@ -365,9 +370,10 @@ def apply_closure(lat, prm, st):
         st.H1[..., x] = fs.H1[..., 0]
         st.H2[..., x] = 0.0
     nx = grid[-1]
+    scale = prm.rho_inf / st.f[..., nx - 3].sum(axis=0)
     for x in (nx - 2, nx - 1):
-        st.f[..., x] = st.f[..., nx - 3]
-        st.rhoE[..., x] = st.rhoE[..., nx - 3]
+        st.f[..., x] = scale * st.f[..., nx - 3]
+        st.rhoE[..., x] = scale * st.rhoE[..., nx - 3]
         st.H1[..., x] = st.H1[..., nx - 3]
         st.H2[..., x] = st.H2[..., nx - 3]
     return st

@@ -319,4 +319,20 @@ __device__ __forceinline__ C energy_flux(const GasT<R>& g, int a, const Cell<L, 
     return flux;
 }
 
+// Outlet of the inflow/outflow closure: the last two columns take the new state of column
+// nx - 3 rescaled by s = rho_inf / rho (populations and total energy alike), so the density there
+// is held at the free-stream value while u and T keep zero gradient. With deviation storage
+// (f~ = f - w, e = rho E - e_ref) the rescaled values are s f~ + (s - 1) w and s e + (s - 1) e_ref.
+// fnew: the column's new f~; fsdev: f~ of the free stream (its sum is rho_inf - 1).
+template <class L, class C, class R>
+__device__ __forceinline__ C outlet_scale(const C* fnew, const R* fsdev) {
+    C drho = 0, dinf = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        drho += fnew[i];
+        dinf += C(fsdev[i]);
+    }
+    return (C(1) + dinf) / (C(1) + drho);
+}
+
 }  // namespace lbmib

@@ -445,11 +445,16 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
             if (xo >= g.nx - 2) return;
         }
         const C enew = C(pe) - ediv + pfE;
-        const int copies = (g.bc_x == 1 && xo == g.nx - 3) ? 3 : 1;
-        for (int c = 0; c < copies; ++c) {
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) Bf[i * N + n + c] = S(pf[i]);
-            Be[n + c] = S(enew);
+        for (int i = 0; i < L::Q; ++i) Bf[i * N + n] = S(pf[i]);
+        Be[n] = S(enew);
+        if (g.bc_x == 1 && xo == g.nx - 3) {               // outlet columns nx - 2, nx - 1
+            const C sc = outlet_scale<L, C>(pf, a.fdev);
+            for (int c = 1; c < 3; ++c) {
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i) Bf[i * N + n + c] = S(sc * pf[i] + (sc - C(1)) * C(L::w[i]));
+                Be[n + c] = S(sc * enew + (sc - C(1)) * a.e_ref);
+            }
         }
     };
 

@@ -250,11 +250,17 @@ __global__ void __launch_bounds__(TPB)
     const int r = a.rows.rowmap[n];
     const C fE = r >= 0 ? C(a.rows.fE[r]) : C(0);
     const C enew = C(A.e[n]) - ediv + fE;
-    const int copies = (g.bc_x == 1 && x == g.nx - 3) ? 3 : 1;
-    for (int k = 0; k < copies; ++k) {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) B.f[i * N + n + k] = S(fnew[i]);
-        B.e[n + k] = S(enew);
+    for (int i = 0; i < L::Q; ++i) B.f[i * N + n] = S(fnew[i]);
+    B.e[n] = S(enew);
+    if (g.bc_x == 1 && x == g.nx - 3) {                    // outlet columns nx - 2, nx - 1
+        const C sc = outlet_scale<L, C>(fnew, a.fs.fdev);
+        const C eref = C(a.fs.e_ref);
+        for (int k = 1; k < 3; ++k) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) B.f[i * N + n + k] = S(sc * fnew[i] + (sc - C(1)) * C(L::w[i]));
+            B.e[n + k] = S(sc * enew + (sc - C(1)) * eref);
+        }
     }
 }
 

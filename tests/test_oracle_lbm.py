@@ -197,3 +197,30 @@ def test_thermal_mode_decay(theta):
     rate = -np.log(h[-1] / h[99]) / 200
     k = 2 * np.pi / 64
     assert abs(rate / (lam * k * k / (7 / 6)) - 1.0) < 0.03
+
+
+@pytest.mark.parametrize('D', [2, 3])
+def test_inflow_outflow_closure(D):
+    """Inlet columns are the free stream; the outlet columns carry column nx-3's u and T at the
+    free-stream density, and the rest of the step does not see the closure."""
+    lat = lattice.for_dim(D)
+    prm = prm_default(u_inf=(0.08, 0.0, 0.0)[:D], T_inf=1.0, bc='inflow_outflow')
+    prm.rho_inf = 1.03
+    grid = (6, 12) if D == 2 else (4, 5, 12)
+    st = rnd_state(lat, grid, 11)
+    new = lbm.lbm_step(lat, prm, st)
+    rho, u, T, _ = lbm.fields(lat, prm, new)
+    fs = lbm.freestream_state(lat, prm, grid)
+    for x in (0, 1):
+        assert np.abs(new.f[..., x] - fs.f[..., x]).max() < 1e-15
+        assert np.abs(new.rhoE[..., x] - fs.rhoE[..., x]).max() < 1e-15
+    nx = grid[-1]
+    assert np.abs(rho[..., nx - 3] - prm.rho_inf).max() > 1e-4          # column nx-3 is not at rho_inf
+    for x in (nx - 2, nx - 1):
+        assert np.abs(rho[..., x] - prm.rho_inf).max() < 1e-14
+        assert np.abs(u[..., x] - u[..., nx - 3]).max() < 1e-14
+        assert np.abs(T[..., x] - T[..., nx - 3]).max() < 1e-14
+        assert np.array_equal(new.H2[..., x], new.H2[..., nx - 3])
+    # away from the closure columns the step equals the periodic step
+    per = lbm.lbm_step(lat, prm_default(u_inf=prm.u_inf, T_inf=1.0, bc='periodic', rho_inf=1.03), st)
+    assert np.abs(new.f[..., 4:nx - 4] - per.f[..., 4:nx - 4]).max() < 1e-15
