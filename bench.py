@@ -189,7 +189,7 @@ def bench_batch(args):
 
 def bench_learned(args):
     """Learned warm start on 256 x 128 ellipses: solver-generated steady data, training, and the
-    time to steady state (FP64, r < 1e-7) warm vs cold on held-out seeds."""
+    time to steady state (FP64, r < 1e-8) warm vs cold on held-out seeds."""
     from paper_2607_07432_amd import learned
     argv = ['--train', str(args.train_cases), '--heldout', str(args.heldout_cases), '--epochs', str(args.epochs),
             '--shape', args.shape, '--clip', str(args.clip), '--warmup-epochs', str(args.warmup_epochs),
@@ -266,7 +266,7 @@ def main():
     ap.add_argument('--eval-shapes', default=None, help='learned workload: bodies of the held-out cases')
     ap.add_argument('--clip', type=float, default=1.0, help='learned workload: gradient-norm clipping (0: off)')
     ap.add_argument('--warmup-epochs', type=float, default=1.0, help='learned workload: linear learning-rate warm-up')
-    ap.add_argument('--eval-tol', type=float, default=1e-7, help='learned workload: residual of the held-out comparison')
+    ap.add_argument('--eval-tol', type=float, default=1e-8, help='learned workload: residual of the held-out comparison')
     args = ap.parse_args()
 
     if args.gpus != 1:

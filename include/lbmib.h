@@ -54,9 +54,9 @@ typedef struct lbm_params {
     int precision;      /* LBM_F32 or LBM_F64: storage and arithmetic of the sweep */
     int bc_x;           /* LBM_BC_PERIODIC or LBM_BC_INFLOW_OUTFLOW along x (y, z periodic).
                            Inflow/outflow: columns 0, 1 are reset to the free stream every step;
-                           columns nx-2, nx-1 take column nx-3 scaled by rho_inf / rho
-                           (populations and rho E; history copied), i.e. density held at
-                           rho_inf, zero gradient of u and T. */
+                           columns nx-2, nx-1 take column nx-3 scaled by p_inf / p
+                           (populations and rho E; history copied), i.e. pressure held at
+                           p_inf, zero gradient of u and T. */
     int kernel;         /* marker kernel: LBM_KERNEL_COS (Eq. (19), d = 2) or LBM_KERNEL_ROMA3 */
     int max_markers;    /* marker capacity reserved in the workspace */
     int with_aC;        /* 1: lattice third-order correction a^C in Eq. (A.9); 0: a^C = 0 */

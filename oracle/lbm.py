@@ -353,11 +353,11 @@ def apply_closure(lat, prm, st):
 
     Columns x = 0, 1 are reset to the free-stream equilibrium (f, rho E, history). Columns
     x = nx-2, nx-1 take column nx-3 with its populations and total energy multiplied by
-    rho_inf / rho_{nx-3}: the density there is the free-stream one, while u and T (and the
-    history terms, copied as they are) have zero gradient. The paper's far field is
-    characteristic and prescribes the free-stream state, which fixes the mean density; a plain
-    copy leaves it free, and a body in the stream then makes the whole field drift slowly
-    without reaching a steady state. y and z stay periodic.
+    (rho_inf T_inf) / (rho T)_{nx-3}: the pressure rho R T there is the free-stream one, while u
+    and T (and the history terms, copied as they are) have zero gradient. The paper's far field
+    is characteristic and prescribes the free-stream pressure; a plain copy leaves the state
+    unanchored, and a body in the stream then makes the whole field drift slowly without reaching
+    a steady state. y and z stay periodic.
     """
     if prm.bc != 'inflow_outflow':
         return st
@@ -370,7 +370,11 @@ def apply_closure(lat, prm, st):
         st.H1[..., x] = fs.H1[..., 0]
         st.H2[..., x] = 0.0
     nx = grid[-1]
-    scale = prm.rho_inf / st.f[..., nx - 3].sum(axis=0)
+    f3, e3 = st.f[..., nx - 3], st.rhoE[..., nx - 3]
+    rho3 = f3.sum(axis=0)
+    u3 = np.einsum('ia,i...->a...', lat.c[:, :D].astype(np.float64), f3) / rho3
+    T3 = (e3 / rho3 - 0.5 * (u3 * u3).sum(axis=0)) / prm.Cv
+    scale = (prm.rho_inf * prm.T_inf) / (rho3 * T3)
     for x in (nx - 2, nx - 1):
         st.f[..., x] = scale * st.f[..., nx - 3]
         st.rhoE[..., x] = scale * st.rhoE[..., nx - 3]

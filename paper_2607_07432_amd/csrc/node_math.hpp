@@ -320,19 +320,33 @@ __device__ __forceinline__ C energy_flux(const GasT<R>& g, int a, const Cell<L, 
 }
 
 // Outlet of the inflow/outflow closure: the last two columns take the new state of column
-// nx - 3 rescaled by s = rho_inf / rho (populations and total energy alike), so the density there
-// is held at the free-stream value while u and T keep zero gradient. With deviation storage
+// nx - 3 rescaled by s = p_inf / p (populations and total energy alike), so the pressure there is
+// the free-stream one while u and T keep zero gradient. p is proportional to the internal energy
+// density rho E - |j|^2 / (2 rho), so s is the ratio of those. With deviation storage
 // (f~ = f - w, e = rho E - e_ref) the rescaled values are s f~ + (s - 1) w and s e + (s - 1) e_ref.
-// fnew: the column's new f~; fsdev: f~ of the free stream (its sum is rho_inf - 1).
-template <class L, class C, class R>
-__device__ __forceinline__ C outlet_scale(const C* fnew, const R* fsdev) {
-    C drho = 0, dinf = 0;
+// fnew, enew: the column's new f~ and e; fsdev, e_ref: the free stream's f~ and rho E.
+template <class L, class C>
+__device__ __forceinline__ C internal_energy(const C* fd, C rhoE) {
+    C drho = 0, j[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        drho += fnew[i];
-        dinf += C(fsdev[i]);
+        drho += fd[i];
+#pragma unroll
+        for (int b = 0; b < L::D; ++b)
+            if (L::c[i][b]) j[b] += C(L::c[i][b]) * fd[i];
     }
-    return (C(1) + dinf) / (C(1) + drho);
+    C jj = 0;
+#pragma unroll
+    for (int b = 0; b < L::D; ++b) jj += j[b] * j[b];
+    return rhoE - C(0.5) * jj / (C(1) + drho);
+}
+
+template <class L, class C, class R>
+__device__ __forceinline__ C outlet_scale(const C* fnew, C enew, const R* fsdev, C e_ref) {
+    C finf[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) finf[i] = C(fsdev[i]);
+    return internal_energy<L, C>(finf, e_ref) / internal_energy<L, C>(fnew, enew + e_ref);
 }
 
 }  // namespace lbmib

@@ -449,7 +449,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         for (int i = 0; i < L::Q; ++i) Bf[i * N + n] = S(pf[i]);
         Be[n] = S(enew);
         if (g.bc_x == 1 && xo == g.nx - 3) {               // outlet columns nx - 2, nx - 1
-            const C sc = outlet_scale<L, C>(pf, a.fdev);
+            const C sc = outlet_scale<L, C>(pf, enew, a.fdev, a.e_ref);
             for (int c = 1; c < 3; ++c) {
 #pragma unroll
                 for (int i = 0; i < L::Q; ++i) Bf[i * N + n + c] = S(sc * pf[i] + (sc - C(1)) * C(L::w[i]));

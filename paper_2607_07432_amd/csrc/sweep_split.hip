@@ -254,8 +254,8 @@ __global__ void __launch_bounds__(TPB)
     for (int i = 0; i < L::Q; ++i) B.f[i * N + n] = S(fnew[i]);
     B.e[n] = S(enew);
     if (g.bc_x == 1 && x == g.nx - 3) {                    // outlet columns nx - 2, nx - 1
-        const C sc = outlet_scale<L, C>(fnew, a.fs.fdev);
         const C eref = C(a.fs.e_ref);
+        const C sc = outlet_scale<L, C>(fnew, enew, a.fs.fdev, eref);
         for (int k = 1; k < 3; ++k) {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) B.f[i * N + n + k] = S(sc * fnew[i] + (sc - C(1)) * C(L::w[i]));

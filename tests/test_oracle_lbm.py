@@ -202,9 +202,10 @@ def test_thermal_mode_decay(theta):
 @pytest.mark.parametrize('D', [2, 3])
 def test_inflow_outflow_closure(D):
     """Inlet columns are the free stream; the outlet columns carry column nx-3's u and T at the
-    free-stream density, and the rest of the step does not see the closure."""
+    free-stream pressure (rho T = rho_inf T_inf), and the rest of the step does not see the
+    closure."""
     lat = lattice.for_dim(D)
-    prm = prm_default(u_inf=(0.08, 0.0, 0.0)[:D], T_inf=1.0, bc='inflow_outflow')
+    prm = prm_default(u_inf=(0.08, 0.0, 0.0)[:D], T_inf=0.95, bc='inflow_outflow')
     prm.rho_inf = 1.03
     grid = (6, 12) if D == 2 else (4, 5, 12)
     st = rnd_state(lat, grid, 11)
@@ -215,12 +216,13 @@ def test_inflow_outflow_closure(D):
         assert np.abs(new.f[..., x] - fs.f[..., x]).max() < 1e-15
         assert np.abs(new.rhoE[..., x] - fs.rhoE[..., x]).max() < 1e-15
     nx = grid[-1]
-    assert np.abs(rho[..., nx - 3] - prm.rho_inf).max() > 1e-4          # column nx-3 is not at rho_inf
+    pinf = prm.rho_inf * prm.T_inf
+    assert np.abs(rho[..., nx - 3] * T[..., nx - 3] - pinf).max() > 1e-4     # not at p_inf before
     for x in (nx - 2, nx - 1):
-        assert np.abs(rho[..., x] - prm.rho_inf).max() < 1e-14
+        assert np.abs(rho[..., x] * T[..., x] - pinf).max() < 1e-14
         assert np.abs(u[..., x] - u[..., nx - 3]).max() < 1e-14
         assert np.abs(T[..., x] - T[..., nx - 3]).max() < 1e-14
         assert np.array_equal(new.H2[..., x], new.H2[..., nx - 3])
     # away from the closure columns the step equals the periodic step
-    per = lbm.lbm_step(lat, prm_default(u_inf=prm.u_inf, T_inf=1.0, bc='periodic', rho_inf=1.03), st)
+    per = lbm.lbm_step(lat, prm_default(u_inf=prm.u_inf, T_inf=0.95, bc='periodic', rho_inf=1.03), st)
     assert np.abs(new.f[..., 4:nx - 4] - per.f[..., 4:nx - 4]).max() < 1e-15
