@@ -251,6 +251,7 @@ int lbm_init_grid(const lbm_params* p, void* ws, size_t bytes, void* stream, lbm
     double uu = 0;
     for (int b = 0; b < 3; ++b) uu += u[b] * u[b];
     a.fs.e_ref = p->rho_inf * (0.5 * uu + Cv * p->T_inf);
+    a.fs.eint_inf = p->rho_inf * Cv * p->T_inf;
     a.fs.rho_inf = p->rho_inf;
     for (int b = 0; b < 3; ++b) a.fs.u_inf[b] = u[b];
     a.fs.T_inf = p->T_inf;

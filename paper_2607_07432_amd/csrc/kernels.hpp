@@ -36,6 +36,7 @@ struct RowsP {
 struct FreeStream {
     double fdev[19];        // f^eq_i - w_i at (rho_inf, u_inf, T_inf)
     double e_ref;           // rho_inf (|u_inf|^2/2 + Cv T_inf): reference of the energy deviation
+    double eint_inf;        // rho_inf Cv T_inf: internal energy density, proportional to p_inf
     double rho_inf, u_inf[3], T_inf;
 };
 
@@ -72,6 +73,7 @@ struct FusedK {
     long long N;
     GasT<C> gas;
     C e_ref;
+    C eint_inf;
     C fdev[19];
     RowsP rows;
 };
@@ -86,6 +88,7 @@ inline FusedK<C> fused_args(const SweepArgs& a) {
     k.N = a.grid.N;
     k.gas = gas_as<C>(a.gas);
     k.e_ref = C(a.fs.e_ref);
+    k.eint_inf = C(a.fs.eint_inf);
     for (int i = 0; i < 19; ++i) k.fdev[i] = C(a.fs.fdev[i]);
     k.rows = a.rows;
     return k;

@@ -324,29 +324,21 @@ __device__ __forceinline__ C energy_flux(const GasT<R>& g, int a, const Cell<L, 
 // the free-stream one while u and T keep zero gradient. p is proportional to the internal energy
 // density rho E - |j|^2 / (2 rho), so s is the ratio of those. With deviation storage
 // (f~ = f - w, e = rho E - e_ref) the rescaled values are s f~ + (s - 1) w and s e + (s - 1) e_ref.
-// fnew, enew: the column's new f~ and e; fsdev, e_ref: the free stream's f~ and rho E.
+// fnew, enew: the column's new f~ and e; eint_inf = rho_inf Cv T_inf.
 template <class L, class C>
-__device__ __forceinline__ C internal_energy(const C* fd, C rhoE) {
+__device__ __forceinline__ C outlet_scale(const C* fnew, C enew, C e_ref, C eint_inf) {
     C drho = 0, j[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        drho += fd[i];
+        drho += fnew[i];
 #pragma unroll
         for (int b = 0; b < L::D; ++b)
-            if (L::c[i][b]) j[b] += C(L::c[i][b]) * fd[i];
+            if (L::c[i][b]) j[b] += C(L::c[i][b]) * fnew[i];
     }
     C jj = 0;
 #pragma unroll
     for (int b = 0; b < L::D; ++b) jj += j[b] * j[b];
-    return rhoE - C(0.5) * jj / (C(1) + drho);
-}
-
-template <class L, class C, class R>
-__device__ __forceinline__ C outlet_scale(const C* fnew, C enew, const R* fsdev, C e_ref) {
-    C finf[L::Q];
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) finf[i] = C(fsdev[i]);
-    return internal_energy<L, C>(finf, e_ref) / internal_energy<L, C>(fnew, enew + e_ref);
+    return eint_inf / ((enew + e_ref) - C(0.5) * jj / (C(1) + drho));
 }
 
 }  // namespace lbmib

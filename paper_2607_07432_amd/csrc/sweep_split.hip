@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(TPB)
     B.e[n] = S(enew);
     if (g.bc_x == 1 && x == g.nx - 3) {                    // outlet columns nx - 2, nx - 1
         const C eref = C(a.fs.e_ref);
-        const C sc = outlet_scale<L, C>(fnew, enew, a.fs.fdev, eref);
+        const C sc = outlet_scale<L, C>(fnew, enew, eref, C(a.fs.eint_inf));
         for (int k = 1; k < 3; ++k) {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) B.f[i * N + n + k] = S(sc * fnew[i] + (sc - C(1)) * C(L::w[i]));
