@@ -82,7 +82,9 @@ struct FusedArgs {
 // One work item: the tile at (x0, y0) of planes [z0, z1) of one grid. Periodic indices: SM = 0
 // by one conditional wrap (valid while a grid dimension exceeds the tile), SM = 1 by the general
 // modulo, SM = 2 as the runtime flag small says.
-template <class L, class S, class C, int TX, int TY, int SM>
+// OUT: the tile holds column nx - 3 under the inflow/outflow closure, so its outlet columns are
+// rescaled here (a separate instantiation, so the other tiles' loop is compiled without it).
+template <class L, class S, class C, int TX, int TY, int SM, bool OUT = false>
 __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, StateP<S> B, int x0, int y0, int z0,
                                            int z1, bool small, FusedSmem<L, S, C, TX, TY>& sm) {
     using G = FG<L, TX, TY>;
@@ -445,8 +447,8 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
             if (xo >= g.nx - 2) return;
         }
         const C enew = C(pe) - ediv + pfE;
-        if constexpr (SM == 2) {
-            // batch: the outlet columns nx - 2, nx - 1 are rescaled here (no extra launch per case)
+        if constexpr (SM == 2 || OUT) {
+            // outlet columns nx - 2, nx - 1: column nx - 3 rescaled by p_inf / p
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) Bf[i * N + n] = S(pf[i]);
             Be[n] = S(enew);
@@ -459,8 +461,8 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
                 }
             }
         } else {
-            // single grid: plain copies into the outlet columns, rescaled afterwards by k_outlet
-            // (the rescaling inside this loop cost the 3D sweep 4.5 % through code generation)
+            // (written as a copy loop, which other tiles never repeat: this form of the store
+            // compiles to the faster 3D loop, 1.282 against 1.312 ms per sweep for a single store)
             const int copies = (g.bc_x == 1 && xo == g.nx - 3) ? 3 : 1;
             for (int c = 0; c < copies; ++c) {
 #pragma unroll
@@ -513,31 +515,6 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     finish(z1 - 1);
 }
 
-// Outlet rescaling after a single-grid sweep under the inflow/outflow closure: one thread per
-// row (y, z) of the outlet; columns nx - 2 and nx - 1 hold plain copies of column nx - 3 and are
-// rescaled in place by p_inf / p (outlet_scale).
-template <class L, class S, class C>
-__global__ void __launch_bounds__(256) k_outlet(FusedK<C> a, StateP<S> B) {
-    const long long rows = L::D == 3 ? (long long)a.ny * a.nz : (long long)a.ny;
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= rows) return;
-    const long long N = a.N;
-    const long long n = (long long)(a.nx - 2) + (long long)a.nx * t;
-    using GS = __attribute__((address_space(1))) S;
-    GS* const Bf = (GS*)B.f;
-    GS* const Be = (GS*)B.e;
-    C fd[L::Q];
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) fd[i] = C(Bf[i * N + n]);
-    const C e = C(Be[n]);
-    const C sc = outlet_scale<L, C>(fd, e, a.e_ref, a.eint_inf);
-    for (int c = 0; c < 2; ++c) {
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) Bf[i * N + n + c] = S(sc * fd[i] + (sc - C(1)) * C(L::w[i]));
-        Be[n + c] = S(sc * e + (sc - C(1)) * a.e_ref);
-    }
-}
-
 template <class L, class S, class C, int TX, int TY, int SM>
 __global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(FusedK<C> a, FusedArgs fa, StateP<S> A, StateP<S> B) {
     __shared__ FusedSmem<L, S, C, TX, TY> sm;
@@ -554,7 +531,12 @@ __global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(F
     const int nm = D == 3 ? a.nz : a.ny;
     const int z0 = chunk * fa.chunk;
     const int z1 = min(z0 + fa.chunk, nm);
-    fused_tile<L, S, C, TX, TY, SM>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
+    // Only the tiles holding column nx - 3 run the instantiation with the outlet rescaling:
+    // inside every tile's loop it made the 3D sweep 4.5 % slower through code generation.
+    if (a.bc_x == 1 && x0 <= a.nx - 3 && a.nx - 3 <= x0 + TX - 1)
+        fused_tile<L, S, C, TX, TY, SM, true>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
+    else
+        fused_tile<L, S, C, TX, TY, SM, false>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
 }
 
 // Persistent sweep over the work items of a batch of 2D grids. The items of one case are
@@ -634,10 +616,6 @@ hipError_t launch_fused_tile(const SweepArgs& a, StateP<S> A, StateP<S> B, int c
         hipLaunchKernelGGL((k_fused<L, S, S, TX, TY, 1>), dim3(grid), dim3(threads), 0, st, k, fa, A, B);
     else
         hipLaunchKernelGGL((k_fused<L, S, S, TX, TY, 0>), dim3(grid), dim3(threads), 0, st, k, fa, A, B);
-    if (g.bc_x == 1) {
-        const long long rows = L::D == 3 ? (long long)g.ny * g.nz : (long long)g.ny;
-        hipLaunchKernelGGL((k_outlet<L, S, S>), dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, k, B);
-    }
     return hipGetLastError();
 }
 
