@@ -4,6 +4,7 @@
 // allocates no device memory. All device work is ordered on the handle's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -311,6 +312,28 @@ int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal, 
     HIPCHK(h, hipStreamSynchronize(st));
     HIPCHK(h, hipMemsetAsync(h->d.rowmap, 0xFF, sizeof(int) * h->N, st));
     h->geom = std::move(g);
+    {
+        // bounding box of the forced nodes; the whole grid if any lies within 2 nodes of an edge
+        // (a tile footprint reaches 2 nodes past the tile and wraps periodically)
+        int* fb = h->fbox;
+        const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz;
+        const int nm = D == 3 ? nz : ny;
+        fb[0] = nx; fb[1] = -1; fb[2] = ny; fb[3] = -1; fb[4] = nm; fb[5] = -1;
+        for (long long n : h->geom.rows) {
+            const int x = (int)(n % nx);
+            const long long q = n / nx;
+            const int y = D == 3 ? (int)(q % ny) : 0;
+            const int mm = D == 3 ? (int)(q / ny) : (int)q;
+            fb[0] = std::min(fb[0], x); fb[1] = std::max(fb[1], x);
+            fb[2] = std::min(fb[2], y); fb[3] = std::max(fb[3], y);
+            fb[4] = std::min(fb[4], mm); fb[5] = std::max(fb[5], mm);
+        }
+        if (fb[0] <= fb[1] && (fb[0] < 2 || fb[1] > nx - 3 || fb[4] < 2 || fb[5] > nm - 3 ||
+                               (D == 3 && (fb[2] < 2 || fb[3] > ny - 3)))) {
+            fb[0] = 0; fb[1] = nx - 1; fb[2] = 0; fb[3] = ny - 1; fb[4] = 0; fb[5] = nm - 1;
+        }
+        if (D == 2 && fb[0] <= fb[1]) { fb[2] = 0; fb[3] = 0; }
+    }
     h->method = method;
     const Geometry& G = h->geom;
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
@@ -390,7 +413,7 @@ int run_steps(lbm_handle* h, int n, hipEvent_t* ev) {
                 if (h->p.sweep == LBM_SWEEP_THREE_PASS)
                     r = launch_split_step<LT, ST, ST>(h->args, A, B, M, fcol, h->stream);
                 else
-                    r = launch_fused_step<LT, ST>(h->args, A, B, h->chunk, h->stream);
+                    r = launch_fused_step<LT, ST>(h->args, A, B, h->chunk, h->fbox, h->stream);
             }
             if (r == hipSuccess && e4) r = hipEventRecord(e4[3], h->stream);
             if (r == hipSuccess && last)

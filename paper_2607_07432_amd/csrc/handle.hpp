@@ -50,6 +50,10 @@ struct lbm_handle {
     int stepped = 0;       // a step has run since the body was set
     int any_step = 0;
     int geom_version = 0;  // incremented by every ib_set_markers
+    // Bounding box of the forced nodes {x min, x max, y min, y max, marching-axis min, max}
+    // (y unused in 2D, where the marching axis is y); empty when min > max. Fused-sweep tiles whose
+    // footprint misses it run without the forcing path.
+    int fbox[6] = {1, 0, 1, 0, 1, 0};
     std::string err;
 };
 

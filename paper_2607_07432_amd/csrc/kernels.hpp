@@ -117,7 +117,9 @@ template <class L, class S, class C>
 hipError_t launch_split_step(const SweepArgs& a, StateP<S> A, StateP<S> B, C* M, C* fcol, hipStream_t st);
 
 template <class L, class S>
-hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, hipStream_t st);
+// fbox: bounding box of the forced nodes (see lbm_handle::fbox).
+hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, const int* fbox,
+                             hipStream_t st);
 
 template <class L, class S>
 hipError_t launch_init_state(const SweepArgs& a, StateP<S> A, hipStream_t st);
