@@ -85,9 +85,10 @@ struct FusedArgs {
 // modulo, SM = 2 as the runtime flag small says.
 // OUT: the tile holds column nx - 3 under the inflow/outflow closure, so its outlet columns are
 // rescaled here. FRC: the tile's footprint (tile + 2 nodes, planes z0 - 2 .. z1 + 1) may hold
-// forced nodes; without it the row map is not read and the forcing path compiles away. Both are
-// separate instantiations so that the common tiles' loop is compiled without the rare paths.
-template <class L, class S, class C, int TX, int TY, int SM, bool OUT = false, bool FRC = true>
+// forced nodes; without it the row map is not read and the forcing path compiles away. INL: the
+// tile holds the inlet columns 0, 1. They are template flags so that the common tiles' loop is
+// compiled without these rare paths.
+template <class L, class S, class C, int TX, int TY, int SM, bool OUT = false, bool FRC = true, bool INL = true>
 __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, StateP<S> B, int x0, int y0, int z0,
                                            int z1, bool small, FusedSmem<L, S, C, TX, TY>& sm) {
     using G = FG<L, TX, TY>;
@@ -315,7 +316,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
                 int copies = 1;
                 bool write = true;
                 if (g.bc_x == 1) {
-                    if (xu < 2) {
+                    if (INL && xu < 2) {
                         Bh[n] = S(0);
                         if (D == 3) Bh[N + n] = S(0);
                         write = false;
@@ -441,7 +442,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         if constexpr (D == 3) ediv += sm.fey[fb][jy1][jx1 - 1] - sm.fey[fb][jy1 - 1][jx1 - 1];
         const long long n = gnode(xo, yo, q);
         if (g.bc_x == 1) {
-            if (xo < 2) {
+            if (INL && xo < 2) {
 #pragma unroll
                 for (int i = 0; i < L::Q; ++i) Bf[i * N + n] = S(a.fdev[i]);
                 Be[n] = S(0);
@@ -535,23 +536,23 @@ __global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(F
     const int z0 = chunk * fa.chunk;
     const int z1 = min(z0 + fa.chunk, nm);
     // Rare paths in their own instantiations (in every tile's loop they slow the 3D sweep through
-    // code generation: the outlet rescaling by 4.5 %, the forcing path by 3 %).
+    // code generation: the outlet rescaling by 4.5 %, the forcing path by 3 %, the inlet reset by
+    // 2.4 %). Four instantiations: the common tile, inlet-only, outlet-only, and one with every
+    // path, which is correct for any tile (forced tiles, small grids, a tile with both closures).
     const bool out = a.bc_x == 1 && x0 <= a.nx - 3 && a.nx - 3 <= x0 + TX - 1;
+    const bool inl = a.bc_x == 1 && x0 < 2;
     const int* fb = fa.fb;
     const bool frc = SM == 1 || (fb[0] <= fb[1] && x0 - 2 <= fb[1] && x0 + TX + 1 >= fb[0] &&
                                  (D == 2 || (y0 - 2 <= fb[3] && y0 + TY + 1 >= fb[2])) && z0 - 2 <= fb[5] &&
                                  z1 + 1 >= fb[4]);
-    if (frc) {
-        if (out)
-            fused_tile<L, S, C, TX, TY, SM, true, true>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
-        else
-            fused_tile<L, S, C, TX, TY, SM, false, true>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
-    } else {
-        if (out)
-            fused_tile<L, S, C, TX, TY, SM, true, false>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
-        else
-            fused_tile<L, S, C, TX, TY, SM, false, false>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
-    }
+    if (!frc && !out && !inl)
+        fused_tile<L, S, C, TX, TY, SM, false, false, false>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
+    else if (!frc && !out)
+        fused_tile<L, S, C, TX, TY, SM, false, false, true>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
+    else if (!frc && !inl)
+        fused_tile<L, S, C, TX, TY, SM, true, false, false>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
+    else
+        fused_tile<L, S, C, TX, TY, SM, true, true, true>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
 }
 
 // Persistent sweep over the work items of a batch of 2D grids. The items of one case are
