@@ -232,6 +232,7 @@ void fill_desc(lbm_batch* b, int tx, int chunk) {
         d.chunk = chunk;
         d.small = (h->p.nx <= tx || h->p.ny < 4) ? 1 : 0;
         d.item0 = items;
+        for (int i = 0; i < 6; ++i) d.fb[i] = h->fbox[i];
         items += d.tiles_x * ((h->p.ny + chunk - 1) / chunk);
         d.marker0 = markers;
         markers += m;

@@ -106,6 +106,7 @@ struct CaseDesc {
     int cur0;               // current state at batch parity 0
     int tiles_x, chunk, small;
     int item0;              // first sweep work item of the case (items: tiles_x per chunk of rows)
+    int fb[6];              // bounding box of the case's forced nodes (lbm_handle::fbox)
     int marker0, row0;      // first marker and first CSR row of the case in the batch numbering
     int part0, nparts, part_len;   // residual partial sums: first, count, nodes per partial
     double resid_scale;     // 1 / (|u_inf| sqrt(N))
@@ -116,8 +117,8 @@ struct CaseDesc {
 template <class L, class S, class C>
 hipError_t launch_split_step(const SweepArgs& a, StateP<S> A, StateP<S> B, C* M, C* fcol, hipStream_t st);
 
-template <class L, class S>
 // fbox: bounding box of the forced nodes (see lbm_handle::fbox).
+template <class L, class S>
 hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, const int* fbox,
                              hipStream_t st);
 

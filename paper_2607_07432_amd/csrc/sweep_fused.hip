@@ -451,7 +451,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
             if (xo >= g.nx - 2) return;
         }
         const C enew = C(pe) - ediv + pfE;
-        if constexpr (SM == 2 || OUT) {
+        if constexpr (OUT) {
             // outlet columns nx - 2, nx - 1: column nx - 3 rescaled by p_inf / p
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) Bf[i * N + n] = S(pf[i]);
@@ -584,8 +584,20 @@ __global__ void __launch_bounds__(TX + 2) k_fused_batch(const CaseDesc<S>* __res
         const FusedK<S> ka = cd.k[cur];
         const StateP<S> A = cd.st[cur], B = cd.st[cur ^ 1];
         const bool small = cd.small != 0;
+        // the same four instantiations as the single-grid sweep, chosen per item
+        const bool out = ka.bc_x == 1 && x0 <= ka.nx - 3 && ka.nx - 3 <= x0 + TX - 1;
+        const bool inl = ka.bc_x == 1 && x0 < 2;
+        const bool frc = small || (cd.fb[0] <= cd.fb[1] && x0 - 2 <= cd.fb[1] && x0 + TX + 1 >= cd.fb[0] &&
+                                   z0 - 2 <= cd.fb[5] && z1 + 1 >= cd.fb[4]);
         __syncthreads();                              // the previous item's LDS reads are done
-        fused_tile<L, S, S, TX, 1, 2>(ka, A, B, x0, 0, z0, z1, small, sm);
+        if (!frc && !out && !inl)
+            fused_tile<L, S, S, TX, 1, 2, false, false, false>(ka, A, B, x0, 0, z0, z1, small, sm);
+        else if (!frc && !out)
+            fused_tile<L, S, S, TX, 1, 2, false, false, true>(ka, A, B, x0, 0, z0, z1, small, sm);
+        else if (!frc && !inl)
+            fused_tile<L, S, S, TX, 1, 2, true, false, false>(ka, A, B, x0, 0, z0, z1, small, sm);
+        else
+            fused_tile<L, S, S, TX, 1, 2, true, true, true>(ka, A, B, x0, 0, z0, z1, small, sm);
     }
 }
 
