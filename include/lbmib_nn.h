@@ -5,7 +5,7 @@
  * part predicts the steady fields (rho, u_x, u_y, T) of a 2D body in a uniform stream from a
  * signed-distance field and the flow parameters, so that the marching can start close to the
  * steady state (a warm start); the plain method then runs to convergence from it, stays the
- * fallback when the prediction is unusable, and judges its error.
+ * fallback when the prediction is unusable, and measures its error.
  *
  * The network is a five-level convolutional U-Net (channels 32, 64, 128, 256, 256; 3x3
  * convolutions with ReLU, 2x2 average pooling, nearest 2x upsampling with skip concatenation,
