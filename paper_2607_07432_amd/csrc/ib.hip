@@ -153,38 +153,56 @@ __global__ void __launch_bounds__(WAVE) k_markers_batch(const CaseDesc<S>* __res
     marker_forces<L, S>(cd.a[cur], cd.mk, cd.st[cur], l - cd.marker0, threadIdx.x);
 }
 
-// Eq. (15): g_i = sum_k s_ik G_k over the CSR row r of node i.
-__device__ __forceinline__ void spread_row(int dim, const MarkersP& mk, const RowsP& rows, int r) {
+// Eq. (15): g_i = sum_k s_ik G_k over the CSR row r of node i. A group of SPREAD_LANES
+// consecutive lanes shares a row (rows hold ~13 entries on the sphere, at most 24): lane j sums
+// the entries j, j + SPREAD_LANES, ... in order, then the group adds its partial sums in a fixed
+// butterfly, so the result does not depend on scheduling. Every lane of the group takes part in
+// the exchange (valid = false for lanes past the last row); lane 0 stores.
+constexpr int SPREAD_LANES = 8;
+
+__device__ __forceinline__ void spread_row(int dim, const MarkersP& mk, const RowsP& rows, int r, int j, bool valid) {
     double f[3] = {0, 0, 0}, e = 0;
-    for (long long k = mk.row_ptr[r]; k < mk.row_ptr[r + 1]; ++k) {
-        const double s = mk.col_s[k];
-        const double* G = mk.G + mk.col_marker[k] * (dim + 2);
-        for (int b = 0; b < dim; ++b) f[b] += s * G[b];
-        e += s * (G[dim] + G[dim + 1]);
+    if (valid) {
+        for (long long k = mk.row_ptr[r] + j; k < mk.row_ptr[r + 1]; k += SPREAD_LANES) {
+            const double s = mk.col_s[k];
+            const double* G = mk.G + mk.col_marker[k] * (dim + 2);
+            for (int b = 0; b < dim; ++b) f[b] += s * G[b];
+            e += s * (G[dim] + G[dim + 1]);
+        }
     }
-    for (int b = 0; b < dim; ++b) rows.fib[(long long)b * rows.nrows + r] = f[b];
-    rows.fE[r] = e;
+#pragma unroll
+    for (int m = SPREAD_LANES / 2; m > 0; m >>= 1) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) f[b] += __shfl_xor(f[b], m, SPREAD_LANES);
+        e += __shfl_xor(e, m, SPREAD_LANES);
+    }
+    if (valid && j == 0) {
+        for (int b = 0; b < dim; ++b) rows.fib[(long long)b * rows.nrows + r] = f[b];
+        rows.fE[r] = e;
+    }
 }
 
-// One lane per forced node.
+// SPREAD_LANES lanes per forced node.
 __global__ void __launch_bounds__(256) k_spread(int dim, MarkersP mk, RowsP rows) {
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= rows.nrows) return;
-    spread_row(dim, mk, rows, r);
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int r = (int)(t / SPREAD_LANES);
+    spread_row(dim, mk, rows, r, (int)(t % SPREAD_LANES), r < rows.nrows);
 }
 
 template <class S>
 __global__ void __launch_bounds__(256) k_spread_batch(const CaseDesc<S>* __restrict__ cases, int ncases, int total,
                                                       int dim) {
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= total) return;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int r = (int)(t / SPREAD_LANES);
+    const bool valid = r < total;
     int lo = 0, hi = ncases - 1;
+    const int rs = valid ? r : total - 1;             // lanes past the end search a real row
     while (lo < hi) {
         const int mid = (lo + hi + 1) / 2;
-        if (cases[mid].row0 <= r) lo = mid; else hi = mid - 1;
+        if (cases[mid].row0 <= rs) lo = mid; else hi = mid - 1;
     }
     const CaseDesc<S>& cd = cases[lo];
-    spread_row(dim, cd.mk, cd.a[0].rows, r - cd.row0);
+    spread_row(dim, cd.mk, cd.a[0].rows, rs - cd.row0, (int)(t % SPREAD_LANES), valid);
 }
 
 // Boundary errors of Eqs. (35), (36), (38) at each marker from the current fields.
@@ -292,7 +310,8 @@ hipError_t launch_markers(const SweepArgs& a, const MarkersP& mk, StateP<S> A, h
 
 hipError_t launch_spread(int dim, const MarkersP& mk, RowsP rows, hipStream_t st) {
     if (rows.nrows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spread, dim3((rows.nrows + 255) / 256), dim3(256), 0, st, dim, mk, rows);
+    const long long lanes = (long long)rows.nrows * SPREAD_LANES;
+    hipLaunchKernelGGL(k_spread, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, dim, mk, rows);
     return hipGetLastError();
 }
 
@@ -319,7 +338,8 @@ hipError_t launch_markers_batch(const CaseDesc<S>* cases, int ncases, int total_
 template <class S>
 hipError_t launch_spread_batch(const CaseDesc<S>* cases, int ncases, int total_rows, int dim, hipStream_t st) {
     if (total_rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_spread_batch<S>), dim3((total_rows + 255) / 256), dim3(256), 0, st, cases, ncases,
+    const long long lanes = (long long)total_rows * SPREAD_LANES;
+    hipLaunchKernelGGL((k_spread_batch<S>), dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st, cases, ncases,
                        total_rows, dim);
     return hipGetLastError();
 }
