@@ -6,7 +6,8 @@
   * a body whose markers all have an empty interior support (inactive: no forcing, counted);
   * grids larger than one tile in every in-plane direction with ragged last tiles (the one-
     conditional-wrap path of the fused sweep), in 2D and 3D, FP64 and FP32;
-  * zero steps leave the state untouched.
+  * zero steps leave the state untouched;
+  * a body 3 cells from a periodic edge of a multi-tile grid (tile footprints wrap onto it).
 """
 import numpy as np
 import pytest
@@ -131,3 +132,24 @@ def test_zero_steps_leave_state(lbmib):
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
     s.close()
+
+
+@pytest.mark.parametrize('dim', [2, 3])
+def test_body_near_a_periodic_edge(lbmib, dim):
+    # markers 3 cells from the low x edge of a periodic multi-tile grid: the last tile's footprint
+    # wraps onto the first columns, and the tiles select the forcing instantiation by the forced
+    # nodes' bounding box, so this checks that no tile misses forcing it needs
+    if dim == 2:
+        case = wl.cylinder_case(nx=300, ny=40, center=(8.3, 20.2), diameter=10.0, markers=32, steps=1)
+    else:
+        case = wl.sphere_case(nx=40, ny=20, nz=16, diameter=6.0, markers=113, steps=1, center=(6.3, 10.1, 7.9),
+                              T_wall_ratio=1.2)
+    case.bc = 'periodic'
+    assert case.X[:, 0].min() > 3.0 and case.X[:, 0].min() < 3.6
+    g = oracle_geometry(case)
+    st = random_state(case, g, seed=13)
+    for sweep in SWEEPS.values():
+        s, ref, f, e, H = march(lbmib, case, st, 2, sweep, with_body=True)
+        print(dim, sweep, 'rel f', rel(f, ref.f), 'rel rhoE', rel(e, ref.rhoE), flush=True)
+        assert rel(f, ref.f) < 1e-12 and rel(e, ref.rhoE) < 1e-12
+        s.close()
