@@ -309,3 +309,77 @@ def test_stencil_leaving_the_grid_is_refused(where):
     with pytest.raises(ValueError):
         ib.build_geometry((20, 20), np.array(X), np.array(n), ib.FODIBM_R)
     ib.build_geometry((20, 20), np.array([[10.2, 10.3]]), np.array([[1.0, 0.0]]), ib.FODIBM_R)
+
+
+def _flat_wall_thermal(method, kind, tv, b, T0=1.1, rho0=1.3, u_wall=0.0):
+    """Markers on the node row y0 (normal +y) over T = T0 + b s, s = y - y0, at density rho0."""
+    nx, ny, y0 = 40, 16, 8.0
+    X = np.array([[float(x), y0] for x in range(4, nx - 4)])
+    n = np.tile([0.0, 1.0], (len(X), 1))
+    g = ib.build_geometry((nx, ny), X, n, method)
+    ys = np.repeat(np.arange(ny), nx).astype(float)
+    T = T0 + b * (ys - y0)
+    mk = ib.Markers(u_wall=np.tile([u_wall, 0.0], (len(X), 1)), t_kind=np.full(len(X), kind, int),
+                    t_value=np.full(len(X), tv))
+    rho = np.full(nx * ny, rho0)
+    u = np.zeros((2, nx * ny))
+    mf = ib.marker_forces(g, mk, _Prm(), rho, rho * u, u, T)
+    mid = [l for l in range(len(X)) if 12 <= X[l, 0] <= nx - 13]
+    return g, mf, mid
+
+
+# Flat wall on a node row with the closed interior (rows y0 and y0 - 1): d_BV = 1/3 (worked values
+# of the flat-wall table); the projection point P = X + 1.5 n sits half-way between rows, where the
+# d = 1 kernel has a zero first moment, and X* lies d_BV below the wall, so for a linear profile
+# T^P* = T0 + 1.5 b and the one-sided T* = T0 - b d_BV exactly.
+DBV_ROW = 1.0 / 3.0
+CV = 5.0 / 6.0
+
+
+@pytest.mark.parametrize('T_w', [1.1, 1.25])
+def test_isothermal_reconstruction_and_heat_source(T_w):
+    # Eq. (27) for T: T^Vt = T_w - (d_BV / d_PB)(T^P* - T_w); Eq. (32): Q = Cv rho* (T^Vt - T*).
+    # With T_w equal to the profile's wall value the target is the profile's value at V, T0 - b d_BV,
+    # and the heat source vanishes; otherwise Q follows the closed form.
+    b, T0, rho0 = 0.023, 1.1, 1.3
+    g, mf, mid = _flat_wall_thermal(ib.FODIBM_R, ib.T_DIRICHLET, T_w, b, T0, rho0)
+    assert np.allclose(g.dBV[mid], DBV_ROW, rtol=0, atol=1e-14)
+    assert np.allclose(mf['TP'][mid], T0 + 1.5 * b, rtol=0, atol=1e-14)
+    assert np.allclose(mf['T'][mid], T0 - b * DBV_ROW, rtol=0, atol=1e-14)
+    Tt = T_w - (DBV_ROW / 1.5) * (T0 + 1.5 * b - T_w)
+    assert np.allclose(mf['Tt'][mid], Tt, rtol=0, atol=1e-14)
+    assert np.allclose(mf['Qib'][mid], CV * rho0 * (Tt - (T0 - b * DBV_ROW)), rtol=0, atol=1e-14)
+    if T_w == T0:
+        assert np.allclose(mf['Tt'][mid], T0 - b * DBV_ROW, rtol=0, atol=1e-14)
+        assert np.abs(mf['Qib'][mid]).max() < 1e-14
+    else:
+        assert np.abs(mf['Qib'][mid]).min() > 1e-3
+
+
+@pytest.mark.parametrize('g_wall', [0.023, -0.011, 0.0])
+def test_neumann_reconstruction_with_gradient(g_wall):
+    # Eq. (29): T^Vt = T^P* - g (d_PB + d_BV). For the linear profile with slope b the target is
+    # T0 + 1.5 b - g (1.5 + d_BV); it equals the profile's value at V when g = b, so
+    # Q = Cv rho (b - g)(1.5 + d_BV).
+    b, T0, rho0 = 0.023, 1.1, 1.3
+    g, mf, mid = _flat_wall_thermal(ib.FODIBM_R, ib.T_NEUMANN, g_wall, b, T0, rho0)
+    Tt = T0 + 1.5 * b - g_wall * (1.5 + DBV_ROW)
+    assert np.allclose(mf['Tt'][mid], Tt, rtol=0, atol=1e-14)
+    assert np.allclose(mf['Qib'][mid], CV * rho0 * (b - g_wall) * (1.5 + DBV_ROW), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize('kind,tv', [(ib.T_DIRICHLET, 1.25), (ib.T_NEUMANN, 0.011)])
+def test_fodibm_thermal_targets(kind, tv):
+    # FODIBM imposes the boundary values themselves (Eq. (22)): T^t = T_w, or for a Neumann wall
+    # the projection-point value carried back over d_PB with the gradient (reading of Eq. (22) with
+    # Eq. (29)'s gradient: T^t = T^P* - g d_PB).
+    b, T0, rho0 = 0.023, 1.1, 1.3
+    g, mf, mid = _flat_wall_thermal(ib.FODIBM, kind, tv, b, T0, rho0)
+    Tt = tv if kind == ib.T_DIRICHLET else T0 + 1.5 * b - tv * 1.5
+    assert np.allclose(mf['Tt'][mid], Tt, rtol=0, atol=1e-14)
+    assert np.allclose(mf['Qib'][mid], CV * rho0 * (Tt - (T0 - b * DBV_ROW)), rtol=0, atol=1e-14)
+
+
+def test_no_thermal_condition_gives_no_heat():
+    _, mf, mid = _flat_wall_thermal(ib.FODIBM_R, ib.T_NONE, 0.0, 0.023)
+    assert np.abs(mf['Qib']).max() == 0.0

@@ -129,3 +129,32 @@ def test_force_population_moments(lat):
     dev = lbm.deviatoric_second_moment(lat, F)
     tr = sum(aF[a, a] for a in range(D))
     assert np.abs(dev - (aF - np.eye(D).reshape((D, D) + (1,) * rho.ndim) * tr / D)).max() < 1e-14
+
+
+def test_printed_h4_is_not_orthogonal():
+    # Eq. (A.6) prints H_4 = H_xxy - H_yyz. With that entry the "3r" set is no longer orthogonal
+    # under the lattice weights (the Gram matrix couples H_4 with H_1, H_3 and H_6), so the
+    # projection with the norms N_k would not reproduce the moments sum f^eq H^(3r)_k = a^(3r)_k;
+    # the pairing of the other five (each sum/difference of the same two components) gives
+    # H_4 = H_xxy - H_yzz, which is orthogonal to every other entry with norm 6 c_s^6.
+    lat = lattice.d3q19()
+    xxy = lat.h3[:, 0, 0, 1]
+    yyz = lat.h3[:, 1, 1, 2]
+    yzz = lat.h3[:, 1, 2, 2]
+    printed = xxy - yyz
+    gram = lambda a, b: float((lat.w * a * b).sum())
+    others = [lat.h3r[:, k] for k in (0, 1, 2, 4, 5)]
+    assert max(abs(gram(printed, h)) for h in others) > 1e-2
+    assert abs(gram(printed, lat.h3r[:, 0])) > 1e-2            # couples with H_1 = H_xxy + H_yzz
+    corrected = xxy - yzz
+    assert np.allclose(corrected, lat.h3r[:, 3], rtol=0, atol=0)
+    assert max(abs(gram(corrected, h)) for h in others) < 1e-16
+    # the printed entry breaks the moment identity of the projected equilibrium
+    rho, u, th = 1.1, np.array([0.12, -0.07, 0.05]), 0.9
+    uuu = rho * u[:, None, None] * u[None, :, None] * u[None, None, :]
+    a_printed = uuu[0, 0, 1] - uuu[1, 1, 2]
+    basis = [lat.h3r[:, 0], lat.h3r[:, 1], lat.h3r[:, 2], printed, lat.h3r[:, 4], lat.h3r[:, 5]]
+    coeffs = lat.tensor3_to_3r(uuu)
+    coeffs[3] = a_printed
+    h3 = sum(b * (a / gram(b, b)) for b, a in zip(basis, coeffs))
+    assert abs(float((lat.w * h3 * printed).sum()) - a_printed) > 1e-5

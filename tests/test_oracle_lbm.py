@@ -226,3 +226,53 @@ def test_inflow_outflow_closure(D):
     # away from the closure columns the step equals the periodic step
     per = lbm.lbm_step(lat, prm_default(u_inf=prm.u_inf, T_inf=0.95, bc='periodic', rho_inf=1.03), st)
     assert np.abs(new.f[..., 4:nx - 4] - per.f[..., 4:nx - 4]).max() < 1e-15
+
+
+@pytest.mark.parametrize('D', [2, 3])
+def test_uniform_forcing_and_force_history(D):
+    """Uniform flow under a uniform force in a periodic box (Eqs. (6), (7), (9), (A.7), (A.9)).
+
+    Every field stays uniform, so gradients vanish and a^F = f u + u f with f = rho a. Mass is
+    fixed, the half-force velocity of Eq. (9) advances by a per step, and (with the energy source
+    chosen to keep T* fixed) so do the second-order moments. Taking the deviatoric second moment
+    of f-bar^{n+1} = f^eq(U^n) + (1 - 1/tau) f^neq(Pi^n) + F^n/2 and adding half the stored
+    history dev sum cc F^n gives, with U^{n+1} = U^n + a,
+        Pi^{n+1} = sigma [ (1 - 1/tau) Pi^n + dev(rho U^n U^n - rho U^{n+1} U^{n+1} + a^F,n) ]
+                 = sigma [ (1 - 1/tau) Pi^n - rho dev(a a) ].
+    Dropping the f u + u f term of a^F, the half history F(t - dt)/2 of Eq. (A.7) or the F/2 of
+    Eq. (6), or using the plain velocity j/rho in a^F, breaks this recursion.
+    """
+    lat = lattice.for_dim(D)
+    grid = (4, 5) if D == 2 else (3, 4, 5)
+    rho0, theta = 1.07, 0.93
+    v = np.array([0.06, -0.03, 0.02][:D])
+    acc = np.array([2e-3, 1.2e-3, -0.8e-3][:D])
+    prm = prm_default(mu=0.04, lam=0.05, T_inf=theta)
+    ones = np.ones(grid)
+    st = lbm.state_from_fields(lat, prm, rho0 * ones, v.reshape((D,) + (1,) * D) * ones, theta * ones)
+    fib = (rho0 * acc).reshape((D,) + (1,) * D) * ones
+    eye = np.eye(D)
+    tau = prm.mu / (rho0 / 3.0) + 0.5
+    dev = lambda t: t - eye * np.trace(t) / D
+    Pi_prev, U_prev = None, None
+    for n in range(6):
+        rho, j, ustar, T = lbm.predicted_macros(lat, prm, st.f, st.rhoE)
+        # energy source that keeps T* fixed: the kinetic energy of j/rho grows by one step of a
+        us_next = ustar + acc.reshape((D,) + (1,) * D)
+        fE = 0.5 * rho * ((us_next ** 2).sum(0) - (ustar ** 2).sum(0))
+        new, dg = lbm.lbm_step(lat, prm, st, fib, fE, return_diag=True)
+        U = dg['u'].reshape(D, -1)[:, 0]
+        Pi = dg['Pi'].reshape(D, D, -1)[:, :, 0]
+        assert np.abs(dg['u'] - U.reshape((D,) + (1,) * D)).max() < 1e-15      # stays uniform
+        assert np.allclose(dg['rho'], rho0, rtol=0, atol=1e-14)
+        assert np.allclose(dg['T'], theta, rtol=0, atol=1e-13)
+        assert np.allclose(U, (j.reshape(D, -1)[:, 0] + 0.5 * rho0 * acc) / rho0, rtol=0, atol=1e-15)
+        if n == 0:
+            assert np.allclose(U, v + 0.5 * acc, rtol=0, atol=1e-15)
+        else:
+            assert np.allclose(U, U_prev + acc, rtol=0, atol=1e-15)
+            expect = prm.sigma * ((1.0 - 1.0 / tau) * Pi_prev - rho0 * dev(np.outer(acc, acc)))
+            assert np.abs(Pi - expect).max() < 1e-15, (n, Pi, expect)
+            assert np.abs(Pi).max() > 1e-9            # the a a term is resolved, not rounded away
+        Pi_prev, U_prev = Pi, U
+        st = new
