@@ -108,7 +108,7 @@ int lbm_init_grid(const lbm_params* p, void* dev_workspace, size_t bytes, void* 
  * Runs the per-geometry precompute on the host in FP64 (supports, interior set, phi of Eq. (16),
  * X* of Eq. (25), d_BV, projection points, W of Eq. (17), node -> marker CSR) and uploads it.
  * Replaces any previous body and clears the force history held at forced nodes.
- * Errors: LBM_E_INVAL (non-finite input, |n| != 1 within 1e-9, a marker within 4 cells of an
+ * Errors: LBM_E_INVAL (non-finite input, |n| != 1 within 1e-12, a marker within 4 cells of an
  * x boundary under the inflow/outflow closure or within 3 cells of any edge, m > max_markers),
  * LBM_E_NOMEM (precomputed lists exceed the workspace), LBM_E_HIP. m = 0 removes the body. */
 int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal,

@@ -294,7 +294,7 @@ int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal, 
             if (x < margin || x > (double)(dims[a] - 1) - margin)
                 return fail(h, LBM_E_INVAL, "marker " + std::to_string(l) + " too close to the domain edge");
         }
-        if (std::fabs(std::sqrt(nn) - 1.0) > 1e-9) return fail(h, LBM_E_INVAL, "normal not of unit length");
+        if (std::fabs(std::sqrt(nn) - 1.0) > 1e-12) return fail(h, LBM_E_INVAL, "normal not of unit length");
         if (!is_fin(t_value[l]) || t_kind[l] < 0 || t_kind[l] > 2)
             return fail(h, LBM_E_INVAL, "bad thermal condition at marker " + std::to_string(l));
     }
