@@ -130,6 +130,21 @@ int lbm_step_timed(lbm_handle* h, int n, double* kernel_ms);
  * Errors: LBM_E_STATE (no body or no step taken since the body was set), LBM_E_HIP. */
 int ib_wall_loads(lbm_handle* h, lbm_loads* out);
 
+/* Marker capacity of ib_wall_loads_noalloc's static scratch (32 bytes per marker, 2 MiB per GPU). */
+#define LBM_NOALLOC_MAX_MARKERS 65536
+
+/* For callers that cannot allocate device memory or use a workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): ib_wall_loads with its
+ * per-marker boundary-error buffer and its reduced-loads buffer taken from a static device array
+ * of the library instead of the handle's workspace. Same inputs, outputs, results and errors as
+ * ib_wall_loads, plus LBM_E_INVAL when the body has more than LBM_NOALLOC_MAX_MARKERS markers and
+ * LBM_E_HIP when the array's device address could not be resolved at lbm_init_grid. Calls no
+ * allocating routine. The array is one per GPU and holds the last call's contents until the
+ * process ends; every call rewrites what it reads. Calls that overlap on one GPU (from several
+ * threads or streams, any handles) race on the array and must be serialised by the caller.
+ * Synchronises the handle's stream. */
+int ib_wall_loads_noalloc(lbm_handle* h, lbm_loads* out);
+
 /* Fields of the current state: rho = sum f, u = sum c f / rho (force-free), T from
  * rho E = rho (|u|^2/2 + Cv T), p = rho R T. dtype LBM_F32 or LBM_F64; on_device = 1 for device
  * pointers (stream-ordered), 0 for host pointers (the call synchronises). u has dim components

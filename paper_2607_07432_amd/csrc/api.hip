@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,6 +20,40 @@ using namespace lbmib;
 namespace {
 
 thread_local std::string g_init_error;
+
+// ---- Static scratch of ib_wall_loads_noalloc ----------------------------------------------------
+// Per-marker boundary errors [LBM_NOALLOC_MAX_MARKERS][4] followed by the 16 reduced loads. Every
+// GPU the library runs on holds its own copy until the process ends. In host code `scratch` names
+// a host-side stand-in, never the device memory: the device address of each GPU's copy is taken
+// once per device with hipGetSymbolAddress (scratch_on_device) and only that address is passed on.
+constexpr size_t kScratchLoads = 16;
+constexpr size_t kScratchDoubles = size_t(LBM_NOALLOC_MAX_MARKERS) * 4 + kScratchLoads;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Device address of the scratch copy of device dev; resolved on the first call for dev, which must
+// run with dev current (lbm_init_grid calls it for the device the handle is created on).
+double* scratch_on_device(int dev, hipError_t* err) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev] && g_scratch_err[dev] == hipSuccess) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e == hipSuccess && ptr)
+            g_scratch_ptr[dev] = static_cast<double*>(ptr);
+        else
+            g_scratch_err[dev] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    }
+    *err = g_scratch_err[dev];
+    return g_scratch_ptr[dev];
+}
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -242,6 +277,11 @@ int lbm_init_grid(const lbm_params* p, void* ws, size_t bytes, void* stream, lbm
     h->Q = Q;
     h->N = (long long)p->nx * p->ny * p->nz;
     h->stream = (hipStream_t)stream;
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;
+    {
+        hipError_t se = hipSuccess;
+        (void)scratch_on_device(h->device, &se);   // once per device, with the handle's device current
+    }
     if (const char* ch = std::getenv("LBMIB_FUSED_CHUNK")) h->chunk = std::atoi(ch);
     layout(*p, (char*)ws, &h->d);
 
@@ -473,21 +513,25 @@ int lbm_residual(lbm_handle* h, double* r) {
     return LBM_OK;
 }
 
-int ib_wall_loads(lbm_handle* h, lbm_loads* out) {
-    if (!h || !out) return LBM_E_INVAL;
-    if (!h->markers_set || !h->stepped) return fail(h, LBM_E_STATE, "no body or no step since it was set");
+namespace {
+
+// Loads of the last step with the per-marker error buffer eps ([m][4]) and the reduced-loads buffer
+// loads (16 doubles) given by the caller of this helper: the handle's workspace or the static scratch.
+int wall_loads_with(lbm_handle* h, lbm_loads* out, double* eps, double* loads) {
     const lbm_params& p = h->p;
     double ur = std::sqrt(p.u_inf[0] * p.u_inf[0] + p.u_inf[1] * p.u_inf[1] + p.u_inf[2] * p.u_inf[2]);
     const double u_ref = ur > 0 ? ur : 1.0;
+    MarkersP mk = h->mk;
+    mk.eps = eps;
     hipError_t e = dispatch(h, [&](auto L, auto S) {
         using LT = decltype(L);
         using ST = decltype(S);
-        return launch_eps<LT, ST>(h->args, h->mk, current<ST>(h), u_ref, p.T_inf, p.ref_len, h->stream);
+        return launch_eps<LT, ST>(h->args, mk, current<ST>(h), u_ref, p.T_inf, p.ref_len, h->stream);
     });
     if (e != hipSuccess) return fail(h, LBM_E_HIP, std::string("eps: ") + hipGetErrorString(e));
-    HIPCHK(h, launch_loads(h->D, h->mk, h->d.loads, h->stream));
+    HIPCHK(h, launch_loads(h->D, mk, loads, h->stream));
     double v[11];
-    HIPCHK(h, hipMemcpyAsync(v, h->d.loads, sizeof(v), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(v, loads, sizeof(v), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     std::memset(out, 0, sizeof(*out));
     for (int b = 0; b < h->D; ++b) out->F[b] = v[b];
@@ -502,6 +546,28 @@ int ib_wall_loads(lbm_handle* h, lbm_loads* out) {
     out->n_inactive = (int)v[10];
     out->n_markers = h->geom.m;
     return LBM_OK;
+}
+
+}  // namespace
+
+int ib_wall_loads(lbm_handle* h, lbm_loads* out) {
+    if (!h || !out) return LBM_E_INVAL;
+    if (!h->markers_set || !h->stepped) return fail(h, LBM_E_STATE, "no body or no step since it was set");
+    return wall_loads_with(h, out, h->mk.eps, h->d.loads);
+}
+
+int ib_wall_loads_noalloc(lbm_handle* h, lbm_loads* out) {
+    if (!h || !out) return LBM_E_INVAL;
+    if (!h->markers_set || !h->stepped) return fail(h, LBM_E_STATE, "no body or no step since it was set");
+    if (h->geom.m > LBM_NOALLOC_MAX_MARKERS)
+        return fail(h, LBM_E_INVAL, "ib_wall_loads_noalloc: " + std::to_string(h->geom.m) + " markers exceed the " +
+                                        std::to_string(LBM_NOALLOC_MAX_MARKERS) + " of the static scratch");
+    hipError_t se = hipSuccess;
+    double* buf = scratch_on_device(h->device, &se);
+    if (!buf) return fail(h, LBM_E_HIP, std::string("static scratch: ") + hipGetErrorString(se));
+    // Every marker's error row is rewritten by the eps kernel and every load by the reduction, so
+    // nothing left from an earlier call (of any handle on this device) is read.
+    return wall_loads_with(h, out, buf, buf + size_t(LBM_NOALLOC_MAX_MARKERS) * 4);
 }
 
 int lbm_fields(lbm_handle* h, int dtype, int on_device, void* rho, void* u, void* T, void* p) {

@@ -38,6 +38,7 @@ struct lbm_handle {
     int D = 0, Q = 0;
     long long N = 0;
     hipStream_t stream = nullptr;
+    int device = -1;       // HIP device current at lbm_init_grid
     lbmib::Dev d{};
     int cur = 0;           // 0: state A is current, 1: state B
     lbmib::SweepArgs args{};

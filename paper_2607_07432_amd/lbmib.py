@@ -20,7 +20,7 @@ SWEEP_FUSED, SWEEP_THREE_PASS = 0, 1
 BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
 
 EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step', 'lbm_step_timed',
-           'ib_wall_loads', 'lbm_fields',
+           'ib_wall_loads', 'ib_wall_loads_noalloc', 'lbm_fields',
            'lbm_set_fields', 'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts',
            'ib_geometry', 'ib_marker_state', 'lbm_destroy', 'lbm_last_error',
            'lbm_batch_workspace_bytes', 'lbm_batch_create', 'lbm_batch_step', 'lbm_batch_step_timed',
@@ -75,6 +75,7 @@ def load_library(path=LIB_PATH):
     lib.lbm_step.argtypes = [vp, i]
     lib.lbm_step_timed.argtypes = [vp, i, dp]
     lib.ib_wall_loads.argtypes = [vp, P(Loads)]
+    lib.ib_wall_loads_noalloc.argtypes = [vp, P(Loads)]
     lib.lbm_fields.argtypes = [vp, i, i, vp, vp, vp, vp]
     lib.lbm_set_fields.argtypes = [vp, i, dp, dp, dp]
     lib.lbm_get_state.argtypes = [vp, dp, dp, dp]
@@ -243,9 +244,11 @@ class Solver:
         self._check(self.lib.lbm_residual(self.h, ctypes.byref(r)))
         return r.value
 
-    def loads(self):
+    def loads(self, noalloc=False):
+        """ib_wall_loads (noalloc=True: ib_wall_loads_noalloc, scratch in the library's static array)."""
         out = Loads()
-        self._check(self.lib.ib_wall_loads(self.h, ctypes.byref(out)))
+        fn = self.lib.ib_wall_loads_noalloc if noalloc else self.lib.ib_wall_loads
+        self._check(fn(self.h, ctypes.byref(out)))
         return dict(F=np.array(out.F[:self.D]), Q_heat=out.Q_heat, Cd=out.Cd, Cl=out.Cl, Nu=out.Nu,
                     eps_dir=out.eps_dir, eps_neu=out.eps_neu, eps_iso=out.eps_iso, n_inactive=out.n_inactive,
                     n_markers=out.n_markers)
