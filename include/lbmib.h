@@ -257,6 +257,12 @@ int lbm_learn_warm_start(lbm_handle* h, const float* d_pred);
 /* Release the handle (not the caller's workspace). */
 void lbm_destroy(lbm_handle* h);
 
+/* Measurement helper: copy `bytes` bytes (a multiple of 16; both pointers 16-byte aligned) from
+ * device memory src to device memory dst with a plain streaming kernel on hip_stream
+ * (asynchronous). It is the yardstick the sweep's bandwidth is compared with (read + write).
+ * Errors: LBM_E_INVAL (size or alignment), LBM_E_HIP. */
+int lbm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
+
 /* Message of the last error on this handle (or of the last failed lbm_init_grid if h is NULL). */
 const char* lbm_last_error(lbm_handle* h);
 

@@ -46,6 +46,8 @@ class Params:
     T_inf: float = 1.0
     bc: str = 'periodic'            # 'periodic' or 'inflow_outflow' (closure along x)
     with_aC: bool = True            # lattice third-order correction inside a^F, Eq. (A.9)
+    aC_form: str = 'diagonal'       # 'diagonal': -delta_ab d_a(rho u_a^3); 'complete': also the
+                                    # theta and xyz terms of the lattice's third-moment defect
     tau_theta: bool = False         # alternative reading: tau = mu/(rho cs2 theta)
     dt_form: str = 'euler'          # d/dt[rho(1-theta)] in Eq. (A.9): 'euler' or 'backward'
     u_zero: float = 1e-7            # MUSCL sign dead zone (U_ZERO); 0 takes sign(u) literally
@@ -206,6 +208,23 @@ def collide(lat, prm, st, fib):
         for a in range(D):
             m = rho * u[a] ** 3
             aC[a, a] = -(at(m, unit(D, a, 1), D) - at(m, unit(D, a, -1), D)) / 2.0
+        if prm.aC_form == 'complete':
+            # The whole Navier-Stokes-level defect of the lattice's third equilibrium moments
+            # (Maxwellian minus lattice): rho cs^2 (theta - 1)(u d + perms) for every component and
+            # rho u_x u_y u_z for the one D3Q19 cannot carry. Chapman-Enskog with a^F entering the
+            # stress with a minus sign turns the first into -cs^2 (u_a d_b g + u_b d_a g),
+            # g = rho (theta - 1), once the paper's isotropic terms are taken out.
+            g = rho * (theta - 1.0)
+            dg = [(at(g, unit(D, b, 1), D) - at(g, unit(D, b, -1), D)) / 2.0 for b in range(D)]
+            for a in range(D):
+                for b in range(D):
+                    aC[a, b] = aC[a, b] - cs2 * (u[a] * dg[b] + u[b] * dg[a])
+            if D == 3:
+                m = rho * u[0] * u[1] * u[2]
+                for (a, b, c) in ((0, 1, 2), (0, 2, 1), (1, 2, 0)):
+                    v = -(at(m, unit(D, c, 1), D) - at(m, unit(D, c, -1), D)) / 2.0
+                    aC[a, b] = aC[a, b] + v
+                    aC[b, a] = aC[b, a] + v
     fu_uf = fib[:, None] * u[None, :] + fib[None, :] * u[:, None]
     aF = (2.0 / D) * eye * rho * cs2 * div - eye * cs2 * dgdt + aC + fu_uf
 

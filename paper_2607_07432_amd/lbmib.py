@@ -22,7 +22,7 @@ BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
 EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step', 'lbm_step_timed',
            'ib_wall_loads', 'ib_wall_loads_noalloc', 'lbm_fields',
            'lbm_set_fields', 'lbm_get_state', 'lbm_set_state', 'lbm_residual', 'ib_geometry_counts',
-           'ib_geometry', 'ib_marker_state', 'lbm_destroy', 'lbm_last_error',
+           'ib_geometry', 'ib_marker_state', 'lbm_destroy', 'lbm_last_error', 'lbm_stream_copy',
            'lbm_batch_workspace_bytes', 'lbm_batch_create', 'lbm_batch_step', 'lbm_batch_step_timed',
            'lbm_batch_set_tile', 'lbm_batch_config', 'lbm_batch_residuals', 'lbm_batch_destroy', 'lbm_batch_last_error',
            'lbm_learn_input', 'lbm_learn_target', 'lbm_learn_warm_start',
@@ -85,6 +85,7 @@ def load_library(path=LIB_PATH):
     lib.ib_geometry.argtypes = [vp, llp, llp, dp, dp, dp, dp, dp, llp, llp, llp, dp, llp]
     lib.ib_marker_state.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
     lib.lbm_destroy.argtypes = [vp]
+    lib.lbm_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.argtypes = [vp]
     lib.lbm_last_error.restype = ctypes.c_char_p

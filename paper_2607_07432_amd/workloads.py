@@ -87,9 +87,54 @@ def flow_units(mach, reynolds, ref_len, T_inf, rho_inf=1.0, gamma=GAMMA, prandtl
     return u, mu, mu * cp / prandtl
 
 
-def reference_temperatures(T_wall_ratio):
-    """T_ref = (T_inf + T_w)/2 (temperatures in units of T_ref): returns (T_inf, T_w)."""
-    t_inf = 2.0 / (1.0 + T_wall_ratio)
+# Choice of the reference temperature T_ref (theta = T / T_ref), which the paper leaves free to set
+# the CFL number of the scheme. Three bounds on theta_inf = T_inf / T_ref:
+#   * the rest population of Eq. (A.3) stays positive with margin where the gas is hottest (the
+#     wall, or the stagnation temperature): theta <= THETA_HOT;
+#   * the free-stream lattice speed u_inf = Ma sqrt(gamma theta_inf / 3) stays below U_LIMIT: the
+#     linearised hybrid step becomes unstable near |u| = 0.31-0.35 whatever theta, sigma or the
+#     readings of Eq. (A.9) (von Neumann analysis of the step; a short-wave energy mode along the
+#     stream), and flow round a body is faster than the free stream;
+#   * the conduction number kappa = lambda / (rho Cv) = gamma u_inf L / (Pr Re) stays below
+#     KAPPA_LIMIT (explicit conduction in the energy update).
+# theta_inf is the largest value that meets all three, and at most 1. A floor comes from the
+# equilibrium itself: its upstream populations stay positive only while theta exceeds about
+# 3 |u| (about 4.2 Ma^2 with u = Ma sqrt(gamma theta / 3)), and runs below it diverged from the
+# impulsive start; theta_inf must stay above THETA_FLOOR_MA2 Ma^2, or the flow is refused
+# (ValueError). With the velocity bound this leaves no theta for Ma above about 0.45.
+THETA_HOT = 1.2
+U_LIMIT = 0.21
+KAPPA_LIMIT = 0.1
+THETA_FLOOR_MA2 = 5.0
+
+
+def lattice_temperature(mach, reynolds, ref_len, T_wall_ratio=None, gamma=GAMMA, prandtl=PRANDTL,
+                        u_limit=None, kappa_limit=None):
+    """theta_inf = T_inf / T_ref for the flow (see the bounds above); T_wall_ratio None means an
+    adiabatic wall, whose hottest point is the stagnation temperature."""
+    u_limit = U_LIMIT if u_limit is None else u_limit
+    kappa_limit = KAPPA_LIMIT if kappa_limit is None else kappa_limit
+    hot = 1.0 + 0.5 * (gamma - 1.0) * mach * mach
+    if T_wall_ratio is not None:
+        hot = max(hot, T_wall_ratio)
+    theta = min(1.0, THETA_HOT / hot)
+    cs_unit = math.sqrt(gamma * R_GAS)                       # sound speed at theta = 1
+    u_cap = u_limit
+    u_cap = min(u_cap, kappa_limit * prandtl * reynolds / (gamma * ref_len))
+    theta = min(theta, (u_cap / (mach * cs_unit)) ** 2)
+    if theta < THETA_FLOOR_MA2 * mach * mach:
+        raise ValueError(f'no reference temperature for Ma {mach:.3f}, Re {reynolds:.1f}, L {ref_len:.1f}: '
+                         f'theta_inf {theta:.3f} below the floor {THETA_FLOOR_MA2 * mach * mach:.3f}')
+    return theta
+
+
+def reference_temperatures(T_wall_ratio, mach=None, reynolds=None, ref_len=None):
+    """(T_inf, T_w) in units of T_ref. With the flow given, T_ref follows lattice_temperature; the
+    older rule T_ref = (T_inf + T_w)/2 is kept when it is not."""
+    if mach is None:
+        t_inf = 2.0 / (1.0 + T_wall_ratio)
+    else:
+        t_inf = lattice_temperature(mach, reynolds, ref_len, T_wall_ratio)
     return t_inf, T_wall_ratio * t_inf
 
 
@@ -154,9 +199,10 @@ def cylinder_case(nx=200, ny=100, center=(60.0, 50.0), diameter=20.0, markers=63
     omega_star the cylinder turns counter-clockwise at omega = 2 omega_star |u_inf| / D, i.e. its
     surface moves at omega_star |u_inf|."""
     if T_wall_ratio is None:
-        T_inf, T_w, kind, tv = 1.0, 1.0, T_NEUMANN, 0.0
+        T_inf = lattice_temperature(mach, reynolds, diameter)
+        T_w, kind, tv = T_inf, T_NEUMANN, 0.0
     else:
-        T_inf, T_w = reference_temperatures(T_wall_ratio)
+        T_inf, T_w = reference_temperatures(T_wall_ratio, mach, reynolds, diameter)
         kind, tv = T_DIRICHLET, T_w
     u, mu, lam = flow_units(mach, reynolds, diameter, T_inf)
     X, n = cylinder_markers(center, diameter / 2.0, markers)
@@ -177,9 +223,10 @@ def sphere_case(nx=384, ny=192, nz=192, diameter=32.0, center=None, mach=0.3, re
     if center is None:
         center = (0.3 * nx, ny / 2.0, nz / 2.0)
     if T_wall_ratio is None:
-        T_inf, T_w, kind, tv = 1.0, 1.0, T_NEUMANN, 0.0
+        T_inf = lattice_temperature(mach, reynolds, diameter)
+        T_w, kind, tv = T_inf, T_NEUMANN, 0.0
     else:
-        T_inf, T_w = reference_temperatures(T_wall_ratio)
+        T_inf, T_w = reference_temperatures(T_wall_ratio, mach, reynolds, diameter)
         kind, tv = T_DIRICHLET, T_w
     u, mu, lam = flow_units(mach, reynolds, diameter, T_inf)
     m = markers if markers is not None else int(round(math.pi * diameter * diameter))
@@ -260,8 +307,9 @@ def conduction_number(case):
 def batched_cases(count=64, seed0=1000, steps=2000, m_lo=64, m_hi=256, kappa_max=0.11, isothermal=False):
     """Uneven 2D ellipse cases: M ~ U{m_lo..m_hi} (64..256), nx = 4M, ny = nx/2, aspect U[1,4],
     angle U[0,90 deg], Ma U[0.1,0.5], Re U[20,200] on L = 2a, adiabatic no-slip wall (isothermal:
-    T_w U[1,1.5] T_inf, drawn in either case). (Ma, Re) pairs whose conduction number exceeds
-    kappa_max are drawn again (the explicit energy update is unstable there)."""
+    T_w U[1,1.5] T_inf, drawn in either case). T_ref follows lattice_temperature; (Ma, Re) pairs
+    it refuses (no admissible T_ref, Ma above about 0.45) or whose conduction number exceeds
+    kappa_max are drawn again."""
     cases = []
     for s in range(count):
         rng = np.random.Generator(np.random.PCG64(seed0 + s))
@@ -272,8 +320,11 @@ def batched_cases(count=64, seed0=1000, steps=2000, m_lo=64, m_hi=256, kappa_max
         while True:
             mach = rng.uniform(0.1, 0.5)
             re = rng.uniform(20.0, 200.0)
-            c = ellipse_case(m, aspect, angle, mach, re, tw if isothermal else None, steps=steps,
-                             name=f'batch{s}')
+            try:
+                c = ellipse_case(m, aspect, angle, mach, re, tw if isothermal else None, steps=steps,
+                                 name=f'batch{s}')
+            except ValueError:
+                continue
             if conduction_number(c) <= kappa_max:
                 break
         cases.append(c)
@@ -283,8 +334,8 @@ def batched_cases(count=64, seed0=1000, steps=2000, m_lo=64, m_hi=256, kappa_max
 def learned_cases(count, seed0=0, nx=256, ny=128, m=64, mach=(0.05, 0.15), reynolds=(15.0, 35.0),
                   kappa_max=0.11, shape='ellipse'):
     """Cases of the learned warm start: one body of perimeter m on nx x ny, seed s drawn from
-    PCG64(seed0 + s), adiabatic no-slip wall, Ma and Re uniform in the given ranges (redrawn
-    while the conduction number exceeds kappa_max).
+    PCG64(seed0 + s), adiabatic no-slip wall, T_inf = T_ref, Ma and Re uniform in the given ranges
+    (redrawn while the conduction number exceeds kappa_max).
       shape 'ellipse': aspect U[1,4], angle U[0,90 deg];
       shape 'star': 5-point star of Eq. (39) with dr/D U[0,0.1], angle U[0,72 deg];
       shape 'mixed': even seeds ellipses, odd seeds stars."""
@@ -304,9 +355,9 @@ def learned_cases(count, seed0=0, nx=256, ny=128, m=64, mach=(0.05, 0.15), reyno
             ma = rng.uniform(*mach)
             re = rng.uniform(*reynolds)
             if kind == 'ellipse':
-                c = ellipse_case(m, aspect, angle, ma, re, None, nx=nx, ny=ny, name=f'learn{seed0 + s}')
+                c = ellipse_case(m, aspect, angle, ma, re, None, nx=nx, ny=ny, name=f'learn{seed0 + s}', t_ref='unit')
             else:
-                c = star_case(m, dr_D, angle, ma, re, None, nx=nx, ny=ny, name=f'star{seed0 + s}')
+                c = star_case(m, dr_D, angle, ma, re, None, nx=nx, ny=ny, name=f'star{seed0 + s}', t_ref='unit')
             if conduction_number(c) <= kappa_max:
                 break
         cases.append(c)
@@ -320,7 +371,8 @@ def star_perimeter(r0, dr, dense=20000):
     return float(np.sum(np.hypot(r, drdt)) * 2.0 * np.pi / dense)
 
 
-def star_case(m, dr_over_D, angle, mach, reynolds, T_wall_ratio=None, steps=2000, name='star', nx=None, ny=None):
+def star_case(m, dr_over_D, angle, mach, reynolds, T_wall_ratio=None, steps=2000, name='star', nx=None, ny=None,
+              t_ref='rule'):
     """Five-point star of Eq. (39) (r = r0 + dr cos 5t, D = 2 r0, dr = dr_over_D D) of perimeter
     m dx with m markers, turned by angle, centre (0.3 nx, 0.5 ny), no-slip wall; walls as in
     ellipse_case. Re and Ma are based on D."""
@@ -328,13 +380,13 @@ def star_case(m, dr_over_D, angle, mach, reynolds, T_wall_ratio=None, steps=2000
     ny = ny if ny is not None else nx // 2
     r0 = m / star_perimeter(1.0, 2.0 * dr_over_D)       # perimeter scales with r0
     dr = 2.0 * dr_over_D * r0
+    D = 2.0 * r0
     if T_wall_ratio is None:
-        T_inf = T_w = 1.0
+        T_inf = T_w = lattice_temperature(mach, reynolds, D) if t_ref == 'rule' else 1.0
         kind, value = T_NEUMANN, 0.0
     else:
-        T_inf, T_w = reference_temperatures(T_wall_ratio)
+        T_inf, T_w = reference_temperatures(T_wall_ratio, mach, reynolds, D)
         kind, value = T_DIRICHLET, T_w
-    D = 2.0 * r0
     u, mu, lam = flow_units(mach, reynolds, D, T_inf)
     c0 = (0.3 * nx, 0.5 * ny)
     X0, n0 = star_markers((0.0, 0.0), r0, dr, m)
@@ -349,7 +401,7 @@ def star_case(m, dr_over_D, angle, mach, reynolds, T_wall_ratio=None, steps=2000
 
 
 def ellipse_case(m, aspect, angle, mach, reynolds, T_wall_ratio=None, steps=2000, name='ellipse',
-                 nx=None, ny=None):
+                 nx=None, ny=None, t_ref='rule'):
     """Ellipse of perimeter m dx (one marker per cell), centre (0.3 nx, 0.5 ny), no-slip wall.
     T_wall_ratio None: adiabatic wall (dT/dn = 0) and T_inf = 1; otherwise an isothermal wall at
     T_wall_ratio T_inf with T_ref = (T_inf + T_w)/2."""
@@ -360,10 +412,10 @@ def ellipse_case(m, aspect, angle, mach, reynolds, T_wall_ratio=None, steps=2000
     a = m / per1
     b = a / aspect
     if T_wall_ratio is None:
-        T_inf = T_w = 1.0
+        T_inf = T_w = lattice_temperature(mach, reynolds, 2.0 * a) if t_ref == 'rule' else 1.0
         kind, value = T_NEUMANN, 0.0
     else:
-        T_inf, T_w = reference_temperatures(T_wall_ratio)
+        T_inf, T_w = reference_temperatures(T_wall_ratio, mach, reynolds, 2.0 * a)
         kind, value = T_DIRICHLET, T_w
     u, mu, lam = flow_units(mach, reynolds, 2.0 * a, T_inf)
     X, n = ellipse_markers((0.3 * nx, 0.5 * ny), a, b, angle, m)

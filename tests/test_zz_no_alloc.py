@@ -36,7 +36,8 @@ def _compare(solver):
 
 
 def _bodies():
-    big = wl.cylinder_case(nx=160, ny=96, center=(50.3, 47.6), diameter=40.0, markers=126, steps=1)
+    big = wl.cylinder_case(nx=160, ny=96, center=(50.3, 47.6), diameter=40.0, markers=126, steps=1,
+                           reynolds=80.0)
     small = wl.cylinder_case(nx=160, ny=96, center=(50.3, 47.6), diameter=14.0, markers=44, steps=1,
                              T_wall_ratio=None)
     return big, small
