@@ -16,7 +16,8 @@ Flat parameter layout: per layer W [cout][taps][cin] then b [cout], in that orde
 
 Activations are NHWC float64 arrays [B, H, W, C]. With emulate_bf16 the forward pass rounds
 weights (not the head), the packed input, every convolution output, and every pooled value to
-bfloat16 (round to nearest even), as the device stores them; the backward pass is exact FP64.
+bfloat16 (round to nearest even), as the device stores them; the backward pass is exact FP64, or
+with emulate_bf16 rounds the activation gradients where the device stores them.
 The convolution is im2col followed by one matrix product; conv_brute is the loop definition.
 Parity of this module is pinned by brute force, adjointness, finite differences and closed forms
 in the tests, not by the paper.
@@ -96,10 +97,14 @@ def col2im(dcols, taps, C):
     return dXp[:, 1:H + 1, 1:W + 1, :]
 
 
-def conv(X, Wt, b, taps, relu):
-    """Pre-activation z and output y of one convolution layer."""
+def conv(X, Wt, b, taps, relu, accum32=False):
+    """Pre-activation z and output y of one convolution layer. accum32: the products are summed
+    in float32 (any order), as a second valid accumulation beside the FP64 one."""
     cout = Wt.shape[0]
-    z = im2col(X, taps) @ Wt.reshape(cout, -1).T + b
+    if accum32:
+        z = (im2col(X, taps).astype(np.float32) @ Wt.reshape(cout, -1).T.astype(np.float32)).astype(np.float64) + b
+    else:
+        z = im2col(X, taps) @ Wt.reshape(cout, -1).T + b
     return z, (np.maximum(z, 0.0) if relu else z)
 
 
@@ -141,8 +146,10 @@ def up_adjoint(G):
     return G.reshape(B, H // 2, 2, W // 2, 2, C).sum(axis=(2, 4))
 
 
-def forward(theta, x_in, emulate_bf16=False):
-    """Network output [B, H, W, 4] and the cache of the backward pass."""
+def forward(theta, x_in, emulate_bf16=False, accum32=False):
+    """Network output [B, H, W, 4] and the cache of the backward pass. accum32: float32 sums in
+    the 3x3 convolutions; with bf16 storage emulated, the distance between the two accumulations
+    is the floor that any FP32-accumulating implementation can be held to."""
     rb = bf16_round if emulate_bf16 else (lambda v: v)
     P = split_params(theta)
     nconv = len(P) - 1
@@ -158,12 +165,12 @@ def forward(theta, x_in, emulate_bf16=False):
         if l > 0:
             x = rb(pool(skips[-1]))
         cache[('in', k)] = x
-        _, a = conv(x, *Ws[k], 9, True)
+        _, a = conv(x, *Ws[k], 9, True, accum32)
         a = rb(a)
         cache[('out', k)] = a
         k += 1
         cache[('in', k)] = a
-        _, s = conv(a, *Ws[k], 9, True)
+        _, s = conv(a, *Ws[k], 9, True, accum32)
         s = rb(s)
         cache[('out', k)] = s
         k += 1
@@ -172,12 +179,12 @@ def forward(theta, x_in, emulate_bf16=False):
     for l in range(LEVELS - 2, -1, -1):
         cat = np.concatenate([up(below), skips[l]], axis=-1)
         cache[('in', k)] = cat
-        _, a = conv(cat, *Ws[k], 9, True)
+        _, a = conv(cat, *Ws[k], 9, True, accum32)
         a = rb(a)
         cache[('out', k)] = a
         k += 1
         cache[('in', k)] = a
-        _, d = conv(a, *Ws[k], 9, True)
+        _, d = conv(a, *Ws[k], 9, True, accum32)
         d = rb(d)
         cache[('out', k)] = d
         k += 1
@@ -194,8 +201,16 @@ def loss(out, tgt, mask=None):
     return float((m[..., None] * (out - tgt) ** 2).sum() / cnt)
 
 
-def backward(theta, cache, out, tgt, mask=None):
-    """Exact FP64 gradient of the masked MSE with respect to the flat parameters."""
+def backward(theta, cache, out, tgt, mask=None, emulate_bf16=False):
+    """Gradient of the masked MSE with respect to the flat parameters, in FP64.
+
+    Exact by default. With emulate_bf16 every activation gradient is rounded to bfloat16 where the
+    device stores one: the data gradient of each convolution (the head's included), the adjoint of
+    the upsampling (four values summed, then rounded) and the skip gradient once the pooling path
+    has been added to it. The ReLU masks are exact; weight and bias gradients are sums of products
+    of those stored values and stay unrounded.
+    """
+    rb = bf16_round if emulate_bf16 else (lambda v: v)
     Ws = cache['Ws']
     shapes = layer_shapes()
     grads = [None] * len(Ws)
@@ -210,7 +225,7 @@ def backward(theta, cache, out, tgt, mask=None):
         dW = dZ.reshape(-1, co).T @ cols.reshape(-1, t * ci)
         grads[k] = (dW.reshape(co, t, ci), dZ.reshape(-1, co).sum(axis=0))
         dcols = dZ @ Ws[k][0].reshape(co, -1)
-        return col2im(dcols, t, ci)
+        return rb(col2im(dcols, t, ci))
 
     k = len(Ws) - 1
     dA = conv_bwd(k, g)                     # head (no activation)
@@ -225,13 +240,13 @@ def backward(theta, cache, out, tgt, mask=None):
         k -= 1
         cu = CH[l + 1]
         d_skip[l] = dcat[..., cu:]
-        dA = up_adjoint(dcat[..., :cu])
+        dA = rb(up_adjoint(dcat[..., :cu]))
     dpool = None
     for l in range(LEVELS - 1, -1, -1):     # bottleneck and encoder
         if l == LEVELS - 1:
             dS = dA
         else:
-            dS = d_skip[l] + pool_adjoint(dpool)
+            dS = rb(d_skip[l] + pool_adjoint(dpool))
         dS = dS * (cache[('out', k)] > 0)
         dA = conv_bwd(k, dS)
         k -= 1

@@ -2,10 +2,14 @@
 
   * grid helpers: input planes (signed distance, parameters, body indicator), normalised
     targets, the warm-start state;
-  * the U-Net: forward against the reference with bf16 rounding emulated at the same points,
-    parameter gradients against the exact FP64 backward, one Adam step, and a short fit.
-The network runs in bf16 with FP32 accumulation, so its bars are relative L2 errors derived
-from the bf16 unit roundoff (2^-8): forward 1e-2, gradients 5e-2 per layer.
+  * the U-Net: forward and parameter gradients against the FP64 reference with bf16 rounding
+    emulated at the points where the device stores bf16, one Adam step, and a short fit.
+The network runs in bf16 with FP32 accumulation; with the storage emulated, what is left is the
+accumulation order. A rounding it flips perturbs the next layer's sums far beyond their own
+rounding error, so flips cascade: the reference summed in float32 instead of FP64 differs from
+itself by 7e-3 on the output and up to 4.3e-2 on the deep layers' gradients. The bars: forward
+1e-2; per-layer gradient relative L2 <= max(2e-2, 1.5x that floor, computed in the test) and
+cosine >= 0.999.
 """
 import numpy as np
 import pytest
@@ -31,8 +35,8 @@ def lbmib():
     return mod
 
 
-def small_case(seed=0):
-    return wl.learned_cases(1, seed0=seed, nx=128, ny=64)[0]
+def small_case(seed=0, shape='ellipse'):
+    return wl.learned_cases(1, seed0=seed, nx=128, ny=64, shape=shape)[0]
 
 
 def relL2(a, b):
@@ -41,9 +45,13 @@ def relL2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def test_learn_input_matches_reference(lbmib):
+@pytest.mark.parametrize('shape,seed', [('ellipse', 3), ('star', 5), ('star', 6)])
+def test_learn_input_matches_reference(lbmib, shape, seed):
+    # the star is not convex: the sign comes from the nearest marker's normal, which the two
+    # sides must pick alike (lowest index on a tie)
     import torch
-    c = small_case(3)
+    c = small_case(seed, shape)
+    assert c.extra.get('shape', 'ellipse') == shape
     s = lbmib.Solver.from_case(c, precision=lbmib.F64)
     out = torch.zeros((64, 128, 4), dtype=torch.float32, device='cuda')
     s.learn_input(out, 16.0, 0.25, -0.5)
@@ -127,12 +135,17 @@ def test_unet_gradients_match_reference(gpu_net, net_case):
     theta, x, tgt, mask = net_case
     _, out, loss, g_gpu, _ = gpu_net
     ref_out, cache = U.forward(theta, x, emulate_bf16=True)
-    g_ref, L_ref = U.backward(theta, cache, ref_out, tgt, mask)
+    g_ref, L_ref = U.backward(theta, cache, ref_out, tgt, mask, emulate_bf16=True)
+    # floor: the same reference with float32 sums in the convolutions; each bf16 rounding that
+    # flips sets off others downstream, so any FP32-accumulating implementation sits about this
+    # far from the FP64 one (measured: 7e-3 on the output, up to 4.3e-2 on the deep layers)
+    f_out, f_cache = U.forward(theta, x, emulate_bf16=True, accum32=True)
+    g_flr, _ = U.backward(theta, f_cache, f_out, tgt, mask, emulate_bf16=True)
     print('loss', loss[0], L_ref, flush=True)
     assert abs(loss[0] - L_ref) <= 1e-2 * L_ref
     assert loss[1] == 4 * mask.sum()
     off = 0
-    worst = 0.0
+    errs = []
     for k, (ci, co, t) in enumerate(U.layer_shapes()):
         n = co * t * ci + co
         a, b = g_gpu[off:off + n], g_ref[off:off + n]
@@ -140,12 +153,14 @@ def test_unet_gradients_match_reference(gpu_net, net_case):
             Wg = a[:co * t * ci].reshape(co, t, ci)
             assert np.all(Wg[..., U.NIN:] == 0.0)
         e = relL2(a, b)
+        floor = relL2(g_flr[off:off + n], b)
         cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
-        worst = max(worst, e)
-        print(f'layer {k} ({ci}->{co}x{t}): grad rel L2 {e:.3e} cos {cos:.6f}', flush=True)
-        assert e <= 5e-2 and cos >= 0.998
+        errs.append((k, e, floor, cos))
+        print(f'layer {k} ({ci}->{co}x{t}): grad rel L2 {e:.3e} (floor {floor:.3e}) cos {cos:.6f}', flush=True)
         off += n
     assert off == U.param_count()
+    for k, e, floor, cos in errs:
+        assert e <= max(2e-2, 1.5 * floor) and cos >= 0.999, (k, e, floor, cos)
 
 
 def test_adam_step_matches_reference(lbmib, gpu_net):
@@ -226,9 +241,11 @@ def test_failed_warm_start_is_flagged_and_cold_start_converges(lbmib):
         s.close()
 
 
-def test_trained_network_shortens_time_to_steady(lbmib):
-    """Train on the steady states the solver reaches from 200 seeds (128 x 64, ellipses of 32
-    markers), then march 8 held-out cases to r < 1e-7 from the warm and from the cold start."""
+@pytest.mark.parametrize('train_shape,eval_shape', [('ellipse', 'ellipse'), ('mixed', 'star')])
+def test_trained_network_shortens_time_to_steady(lbmib, train_shape, eval_shape):
+    """Train on the steady states the solver reaches from 200 seeds (128 x 64, bodies of 32
+    markers: ellipses, or ellipses and five-point stars of Eq. (39) on alternate seeds), then march
+    8 held-out cases (ellipses, or stars) to r < 1e-7 from the warm and from the cold start."""
     from paper_2607_07432_amd import learned
     nx, ny, tol = 128, 64, 1e-7
     orig = wl.learned_cases
@@ -238,13 +255,13 @@ def test_trained_network_shortens_time_to_steady(lbmib):
 
     wl.learned_cases = small
     try:
-        X, T, kept, _ = learned.generate(list(range(200)), nx, ny, tol, 40000, 250)
+        X, T, kept, _ = learned.generate(list(range(200)), nx, ny, tol, 40000, 250, shape=train_shape)
         print('steady training cases', len(kept), flush=True)
         assert len(kept) >= 100
         net, hist, _, _ = learned.train(X, T, epochs=40, batch=8, lr=1e-3)
         print('loss', hist[0], '->', hist[-1], flush=True)
         assert hist[-1] < 0.2 * hist[0]
-        ev = learned.evaluate(net, list(range(10000, 10008)), nx, ny, tol, 40000, 250)
+        ev = learned.evaluate(net, list(range(10000, 10008)), nx, ny, tol, 40000, 250, shape=eval_shape)
     finally:
         wl.learned_cases = orig
     print(ev, flush=True)

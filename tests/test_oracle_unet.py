@@ -85,6 +85,36 @@ def test_backward_matches_finite_differences(tiny):
         assert abs(fdi - g[i]) <= 1e-5 * max(abs(fdi), 1e-8) + 1e-10, i
 
 
+def test_bf16_emulated_backward_stays_within_rounding_of_exact(tiny):
+    # storing activation gradients in bfloat16 perturbs each layer's gradient by a few units of
+    # 2^-8 at most, and does perturb it (the rounding is applied on the way down)
+    theta, x, tgt, mask = tiny
+    out, cache = U.forward(theta, x, emulate_bf16=True)
+    g_ex, L_ex = U.backward(theta, cache, out, tgt, mask)
+    g_bf, L_bf = U.backward(theta, cache, out, tgt, mask, emulate_bf16=True)
+    assert L_ex == L_bf
+    off = 0
+    for k, (ci, co, t) in enumerate(U.layer_shapes()):
+        n = co * t * ci + co
+        a, b = g_bf[off:off + n], g_ex[off:off + n]
+        e = np.linalg.norm(a - b) / np.linalg.norm(b)
+        if k < len(U.layer_shapes()) - 1:
+            assert 0.0 < e <= 2e-2, (k, e)
+        else:
+            assert e == 0.0                    # the head's gradient uses no stored gradient
+        off += n
+
+
+def test_float32_accumulation_is_a_small_perturbation(tiny):
+    # the float32-sum variant of the forward pass stays within the FP32 rounding of the exact one
+    # (no bf16 storage: nothing cascades), and differs from it
+    theta, x, tgt, mask = tiny
+    o64, _ = U.forward(theta, x)
+    o32, _ = U.forward(theta, x, accum32=True)
+    e = np.linalg.norm(o32 - o64) / np.linalg.norm(o64)
+    assert 0.0 < e < 1e-5
+
+
 def test_adam_first_step_closed_form():
     theta = np.array([1.0, -2.0, 0.5])
     g = np.array([0.3, -0.1, 0.0])
