@@ -40,7 +40,7 @@ enum {
     LBM_E_NONFINITE = -5   /* a non-finite value was detected by the step check */
 };
 
-enum { LBM_BC_PERIODIC = 0, LBM_BC_INFLOW_OUTFLOW = 1 };
+enum { LBM_BC_PERIODIC = 0, LBM_BC_INFLOW_OUTFLOW = 1, LBM_BC_CHARACTERISTIC = 2 };
 enum { LBM_IB_DIBM = 0, LBM_IB_FODIBM = 1, LBM_IB_FODIBM_R = 2 };
 enum { LBM_KERNEL_COS = 0, LBM_KERNEL_ROMA3 = 1 };
 enum { LBM_T_NONE = 0, LBM_T_DIRICHLET = 1, LBM_T_NEUMANN = 2 };
@@ -52,11 +52,17 @@ typedef struct lbm_params {
     int dim;            /* 2 (D2Q9) or 3 (D3Q19, Appendix A) */
     int nx, ny, nz;     /* grid size: nx >= 5, ny >= 2, nz >= 2 in 3D and nz = 1 in 2D */
     int precision;      /* LBM_F32 or LBM_F64: storage and arithmetic of the sweep */
-    int bc_x;           /* LBM_BC_PERIODIC or LBM_BC_INFLOW_OUTFLOW along x (y, z periodic).
-                           Inflow/outflow: columns 0, 1 are reset to the free stream every step;
-                           columns nx-2, nx-1 take column nx-3 scaled by p_inf / p
-                           (populations and rho E; history copied), i.e. pressure held at
-                           p_inf, zero gradient of u and T. */
+    int bc_x;           /* LBM_BC_PERIODIC, LBM_BC_INFLOW_OUTFLOW or LBM_BC_CHARACTERISTIC
+                           along x (y, z periodic). Inflow/outflow: columns 0, 1 are reset to the
+                           free stream every step; columns nx-2, nx-1 take column nx-3 scaled
+                           by p_inf / p (populations and rho E; history copied), i.e. pressure
+                           held at p_inf, zero gradient of u and T. Characteristic: the same
+                           inlet; columns nx-2, nx-1 advance by the locally one-dimensional
+                           characteristic relations (Sec. 2.4 names Poinsot and Lele's
+                           conditions for the far field), outgoing waves leaving freely and the
+                           incoming one relaxed to p_inf with sigma_c; populations are the
+                           equilibrium of Eq. (A.3) at the new fields plus the non-equilibrium
+                           part of column nx-3. Batches take the first two only. */
     int kernel;         /* marker kernel: LBM_KERNEL_COS (Eq. (19), d = 2) or LBM_KERNEL_ROMA3 */
     int max_markers;    /* marker capacity reserved in the workspace */
     int with_aC;        /* 1: lattice third-order correction a^C in Eq. (A.9); 0: a^C = 0 */
@@ -72,6 +78,9 @@ typedef struct lbm_params {
     double ref_area;    /* reference area for Cd, Cl (a length in 2D) */
     double surface;     /* wetted surface for Nu (a perimeter in 2D) */
     double T_wall;      /* wall temperature used in Nu */
+    double sigma_c;     /* characteristic outlet: relaxation of the incoming wave,
+                           L1 = sigma_c (1 - Ma^2) c / nx (p - p_inf); 0 = non-reflecting
+                           (0.25 is usual); finite and >= 0; unused by the other closures */
 } lbm_params;
 
 /* Loads of the last step (FP64). F = -sum_l F_l W_l (force on the body), Q_heat = sum_l Q_l W_l,

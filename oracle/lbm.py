@@ -44,7 +44,9 @@ class Params:
     rho_inf: float = 1.0
     u_inf: tuple = (0.0, 0.0, 0.0)
     T_inf: float = 1.0
-    bc: str = 'periodic'            # 'periodic' or 'inflow_outflow' (closure along x)
+    bc: str = 'periodic'            # 'periodic', 'inflow_outflow' (closure along x), or
+                                    # 'characteristic' (the same inlet, characteristic outlet)
+    sigma_c: float = 0.25           # characteristic outlet: relaxation of the incoming wave to p_inf
     with_aC: bool = True            # lattice third-order correction inside a^F, Eq. (A.9)
     aC_form: str = 'diagonal'       # 'diagonal': -delta_ab d_a(rho u_a^3); 'complete': also the
                                     # theta and xyz terms of the lattice's third-moment defect
@@ -382,7 +384,7 @@ def apply_closure(lat, prm, st):
     unanchored, and a body in the stream then makes the whole field drift slowly without reaching
     a steady state. y and z stay periodic.
     """
-    if prm.bc != 'inflow_outflow':
+    if prm.bc not in ('inflow_outflow', 'characteristic'):
         return st
     D = lat.D
     grid = st.rhoE.shape
@@ -393,6 +395,8 @@ def apply_closure(lat, prm, st):
         st.H1[..., x] = fs.H1[..., 0]
         st.H2[..., x] = 0.0
     nx = grid[-1]
+    if prm.bc == 'characteristic':
+        return st                   # the outlet columns are set by characteristic_outlet
     f3, e3 = st.f[..., nx - 3], st.rhoE[..., nx - 3]
     rho3 = f3.sum(axis=0)
     u3 = np.einsum('ia,i...->a...', lat.c[:, :D].astype(np.float64), f3) / rho3
@@ -404,6 +408,61 @@ def apply_closure(lat, prm, st):
         st.H1[..., x] = st.H1[..., nx - 3]
         st.H2[..., x] = st.H2[..., nx - 3]
     return st
+
+
+def characteristic_outlet(lat, prm, old, new):
+    """Characteristic (locally one-dimensional, inviscid) outlet on columns x = nx-2, nx-1, after
+    the closure of the inlet (the far-field treatment the paper takes from Poinsot and Lele).
+
+    The primitive variables of each column advance one step by the LODI relations, with the
+    amplitudes of the waves leaving the domain from first-order upwind (backward) differences of
+    the old state, and the amplitude entering it relaxed to the free-stream pressure,
+    L1 = K (p - p_inf), K = sigma_c (1 - Ma^2) c / nx (sigma_c = 0 makes the outlet non-reflecting):
+      L5 = (u + c)(dp + rho c du),  L2 = u (c^2 drho - dp),  L3 = u dv,  L4 = u dw,
+      rho' = rho - (L2 + (L5 + L1)/2)/c^2,  p' = p - (L5 + L1)/2,  u' = u - (L5 - L1)/(2 rho c),
+      v' = v - L3,  w' = w - L4,
+    with p = rho R T, c^2 = gamma p / rho, u the x velocity; an amplitude whose speed (u or u + c)
+    is negative would enter the domain and is set to zero. The populations are the equilibrium
+    of Eq. (A.3) at the new (rho, u, T) plus the non-equilibrium part of column nx-3 in the new
+    state; rho E, [rho (1 - theta)] follow from the new fields and the force history is that of
+    column nx-3, as in the other closure.
+    """
+    D = lat.D
+    R = prm.R
+    nx = new.rhoE.shape[-1]
+    rho, _, u, T = predicted_macros(lat, prm, old.f, old.rhoE)
+    p = rho * R * T
+    # non-equilibrium part of column nx-3 of the new state
+    rn, _, un, Tn = predicted_macros(lat, prm, new.f[..., nx - 3], new.rhoE[..., nx - 3])
+    fneq = new.f[..., nx - 3] - equilibrium(lat, rn, un, Tn)
+    out_f, out_e, out_h1 = [], [], []
+    for xb in (nx - 2, nx - 1):
+        r, pp, T0 = rho[..., xb], p[..., xb], T[..., xb]
+        uv = u[..., xb]
+        c = np.sqrt(prm.gamma * pp / r)
+        dr = r - rho[..., xb - 1]
+        dp = pp - p[..., xb - 1]
+        du = uv - u[..., xb - 1]
+        ux = uv[0]
+        L5 = np.where(ux + c > 0, (ux + c) * (dp + r * c * du[0]), 0.0)
+        L2 = np.where(ux > 0, ux * (c * c * dr - dp), 0.0)
+        Lt = [np.where(ux > 0, ux * du[a], 0.0) for a in range(1, D)]
+        p_inf = prm.rho_inf * R * prm.T_inf
+        K = prm.sigma_c * (1.0 - (ux / c) ** 2) * c / nx
+        L1 = K * (pp - p_inf)
+        r_n = r - (L2 + 0.5 * (L5 + L1)) / (c * c)
+        p_n = pp - 0.5 * (L5 + L1)
+        u_n = np.stack([ux - (L5 - L1) / (2.0 * r * c)] + [uv[a] - Lt[a - 1] for a in range(1, D)])
+        T_n = p_n / (r_n * R)
+        out_f.append(equilibrium(lat, r_n, u_n, T_n) + fneq)
+        out_e.append(r_n * (0.5 * (u_n * u_n).sum(axis=0) + prm.Cv * T_n))
+        out_h1.append(r_n * (1.0 - T_n))
+    for k, xb in enumerate((nx - 2, nx - 1)):
+        new.f[..., xb] = out_f[k]
+        new.rhoE[..., xb] = out_e[k]
+        new.H1[..., xb] = out_h1[k]
+        new.H2[..., xb] = new.H2[..., nx - 3]
+    return new
 
 
 def lbm_step(lat, prm, st, fib=None, fE=None, return_diag=False):
@@ -427,6 +486,8 @@ def lbm_step(lat, prm, st, fib=None, fE=None, return_diag=False):
     new = State(f=stream(lat, col['fcol']), rhoE=rhoE_new, H1=col['H1_new'], H2=col['H2_new'],
                 step=st.step + 1)
     new = apply_closure(lat, prm, new)
+    if prm.bc == 'characteristic':
+        new = characteristic_outlet(lat, prm, st, new)
     if return_diag:
         col.update(Frho=Frho, Fmom=Fmom, FE=FE)
         return new, col

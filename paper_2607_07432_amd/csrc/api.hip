@@ -88,7 +88,7 @@ size_t layout(const lbm_params& p, char* base, Dev* d) {
     o.hB = L.take<char>((D - 1) * N * s);
     o.work = L.take<char>((D + 2 + Q) * N * s);
     o.rowmap = L.take<int>(N);
-    o.partials = L.take<double>(2 * 1024);
+    o.partials = L.take<double>(2 * RESID_PARTS_MAX);
     o.resid = L.take<double>(2);
     o.loads = L.take<double>(16);
     o.flag = L.take<int>(4);
@@ -217,7 +217,10 @@ int validate_params(const lbm_params* p, std::string& why) {
         return why = "grid too small (nx >= 5, ny >= 2, and nz >= 2 in 3D)", LBM_E_INVAL;
     if (p->dim == 2 && p->nz != 1) return why = "nz must be 1 in 2D", LBM_E_INVAL;
     if (p->precision != LBM_F32 && p->precision != LBM_F64) return why = "precision must be 32 or 64", LBM_E_INVAL;
-    if (p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_INFLOW_OUTFLOW) return why = "bad bc_x", LBM_E_INVAL;
+    if (p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_INFLOW_OUTFLOW && p->bc_x != LBM_BC_CHARACTERISTIC)
+        return why = "bad bc_x", LBM_E_INVAL;
+    if (p->bc_x == LBM_BC_CHARACTERISTIC && !(is_fin(p->sigma_c) && p->sigma_c >= 0.0))
+        return why = "sigma_c must be finite and >= 0", LBM_E_INVAL;
     if (p->kernel != LBM_KERNEL_COS && p->kernel != LBM_KERNEL_ROMA3) return why = "bad kernel", LBM_E_INVAL;
     if (p->max_markers < 0) return why = "max_markers < 0", LBM_E_INVAL;
     const double vals[] = {p->gamma, p->mu, p->lambda_, p->sigma, p->rho_inf, p->u_inf[0], p->u_inf[1],
@@ -329,7 +332,7 @@ int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal, 
             if (!is_fin(x) || !is_fin(nv) || !is_fin(u_wall[l * D + a]))
                 return fail(h, LBM_E_INVAL, "non-finite marker data at marker " + std::to_string(l));
             nn += nv * nv;
-            const double margin = (a == 0 && h->p.bc_x == LBM_BC_INFLOW_OUTFLOW) ? 4.0 : 3.0;
+            const double margin = (a == 0 && h->p.bc_x != LBM_BC_PERIODIC) ? 4.0 : 3.0;
             if (x < margin || x > (double)(dims[a] - 1) - margin)
                 return fail(h, LBM_E_INVAL, "marker " + std::to_string(l) + " too close to the domain edge");
         }
@@ -448,16 +451,25 @@ int run_steps(lbm_handle* h, int n, hipEvent_t* ev) {
             if (r == hipSuccess && e4) r = hipEventRecord(e4[2], h->stream);
             ST* M = (ST*)h->d.work;
             ST* fcol = M + (size_t)(h->D + 2) * h->N;
+            // the last step's residual: formed by the fused sweep where it can, else k_residual
+            int rparts = 0;
             if (r == hipSuccess) {
                 if (h->p.sweep == LBM_SWEEP_THREE_PASS)
                     r = launch_split_step<LT, ST, ST>(h->args, A, B, M, fcol, h->stream);
                 else
-                    r = launch_fused_step<LT, ST>(h->args, A, B, h->chunk, h->fbox, h->stream);
+                    r = launch_fused_step<LT, ST>(h->args, A, B, h->chunk, h->fbox, h->stream,
+                                                  last ? h->d.partials : nullptr, RESID_PARTS_MAX, &rparts);
             }
+            if (r == hipSuccess && h->p.bc_x == LBM_BC_CHARACTERISTIC)
+                r = launch_outlet_char<LT, ST>(h->args, A, B, h->p.sigma_c, h->stream);
             if (r == hipSuccess && e4) r = hipEventRecord(e4[3], h->stream);
-            if (r == hipSuccess && last)
-                r = launch_residual<LT, ST>(h->args, A, B, h->d.partials, residual_parts(h->N), h->d.resid,
-                                            h->stream);
+            if (r == hipSuccess && last) {
+                if (rparts > 0)
+                    r = launch_residual_final<LT>(h->args, h->d.partials, rparts, h->d.resid, h->stream);
+                else
+                    r = launch_residual<LT, ST>(h->args, A, B, h->d.partials, residual_parts(h->N), h->d.resid,
+                                                h->stream);
+            }
             return r;
         });
         if (e != hipSuccess) return fail(h, LBM_E_HIP, std::string("lbm_step: ") + hipGetErrorString(e));

@@ -191,6 +191,8 @@ int validate_cases(lbm_handle* const* hs, int n, std::string& why) {
         const lbm_handle* h = hs[c];
         if (!h) return why = "case " + std::to_string(c) + " is NULL", LBM_E_INVAL;
         if (h->D != 2) return why = "batches hold 2D (D2Q9) grids only", LBM_E_INVAL;
+        if (h->p.bc_x == LBM_BC_CHARACTERISTIC)
+            return why = "batches support the periodic and inflow/outflow closures only", LBM_E_INVAL;
         if (h->p.precision != hs[0]->p.precision) return why = "all cases must share the precision", LBM_E_INVAL;
         if (h->stream != hs[0]->stream) return why = "all cases must share one stream", LBM_E_INVAL;
         for (int k = 0; k < c; ++k)

@@ -10,7 +10,8 @@ namespace lbmib {
 struct GridP {
     int nx, ny, nz;
     long long N;
-    int bc_x;           // 0 periodic, 1 inflow/outflow closure along x
+    int bc_x;           // 0 periodic; 1 inflow/outflow closure along x; 2 the same inlet with the
+                        // characteristic outlet (the sweep leaves columns nx-2, nx-1 to it)
 };
 
 // Ping-pong state (storage type S): f~[Q][N] (f - w), e[N] (rho E - e_ref), h2[D-1][N]
@@ -117,10 +118,12 @@ struct CaseDesc {
 template <class L, class S, class C>
 hipError_t launch_split_step(const SweepArgs& a, StateP<S> A, StateP<S> B, C* M, C* fcol, hipStream_t st);
 
-// fbox: bounding box of the forced nodes (see lbm_handle::fbox).
+// fbox: bounding box of the forced nodes (see lbm_handle::fbox). With rpart (capacity rcap
+// pairs) the sweep also writes the step's residual partials, one (sum, non-finite flag) pair per
+// workgroup, and sets *rparts to their count; *rparts = 0 when this grid cannot (run k_residual).
 template <class L, class S>
 hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, const int* fbox,
-                             hipStream_t st);
+                             hipStream_t st, double* rpart = nullptr, int rcap = 0, int* rparts = nullptr);
 
 template <class L, class S>
 hipError_t launch_init_state(const SweepArgs& a, StateP<S> A, hipStream_t st);
@@ -136,6 +139,12 @@ hipError_t launch_import(const SweepArgs& a, StateP<S> A, int comp, const double
 template <class L, class S>
 hipError_t launch_residual(const SweepArgs& a, StateP<S> Old, StateP<S> New, double* partials, int nparts,
                            double* out, hipStream_t st);
+// Characteristic outlet (outlet.hip): columns nx-2, nx-1 of New from the LODI relations on Old.
+template <class L, class S>
+hipError_t launch_outlet_char(const SweepArgs& a, StateP<S> Old, StateP<S> New, double sigma_c, hipStream_t st);
+// The final reduction alone, over nparts partial pairs written by a sweep.
+template <class L>
+hipError_t launch_residual_final(const SweepArgs& a, const double* partials, int nparts, double* out, hipStream_t st);
 
 // Immersed boundary.
 template <class L, class S>
@@ -148,6 +157,9 @@ hipError_t launch_loads(int dim, const MarkersP& mk, double* out, hipStream_t st
 hipError_t launch_rowmap(const long long* rows, int nrows, int* rowmap, hipStream_t st);
 
 int residual_parts(long long N);
+// Capacity of the residual partials buffer, in (sum, flag) pairs: k_residual uses at most 1024,
+// a fused sweep one per workgroup.
+constexpr int RESID_PARTS_MAX = 8192;
 
 // Batch of 2D grids. Sweep tile widths: 62, 126 or 254 nodes (64, 128, 256 threads).
 template <class L, class S>

@@ -76,6 +76,7 @@ struct FusedArgs {
     int tiles_x, tiles_y, chunks, chunk, total, per_xcd;
     int small;      // a grid dimension is smaller than a tile plus halo: use the general modulo
     int fb[6];      // bounding box of the forced nodes (x, y, marching axis; empty if min > max)
+    double* rpart;  // residual partials (sum of |u_new - u_old|^2, non-finite flag) per workgroup
 };
 
 }  // namespace
@@ -88,9 +89,13 @@ struct FusedArgs {
 // forced nodes; without it the row map is not read and the forcing path compiles away. INL: the
 // tile holds the inlet columns 0, 1. They are template flags so that the common tiles' loop is
 // compiled without these rare paths.
-template <class L, class S, class C, int TX, int TY, int SM, bool OUT = false, bool FRC = true, bool INL = true>
+// RES: the step's residual terms are accumulated on the way (FP64, from the stored states):
+// racc += |u_new - u_old|^2 over the tile's output nodes, rbad = 1 on a non-finite value.
+template <class L, class S, class C, int TX, int TY, int SM, bool OUT = false, bool FRC = true, bool INL = true,
+          bool RES = false>
 __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, StateP<S> B, int x0, int y0, int z0,
-                                           int z1, bool small, FusedSmem<L, S, C, TX, TY>& sm) {
+                                           int z1, bool small, FusedSmem<L, S, C, TX, TY>& sm, double* racc = nullptr,
+                                           int* rbad = nullptr) {
     using G = FG<L, TX, TY>;
     constexpr int D = L::D;
     const FusedK<C>& g = a;
@@ -224,6 +229,19 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         return c;
     };
 
+    // ---- residual (RES): u^n of the own node from its collision, kept until its output plane
+    // is finished two planes later (ru0: the older, ru1: the newer collided plane)
+    double ru_new[3] = {0, 0, 0}, ru0[3] = {0, 0, 0}, ru1[3] = {0, 0, 0};
+    auto res_push = [&]() {
+        if constexpr (RES) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                ru0[b] = ru1[b];
+                ru1[b] = ru_new[b];
+            }
+        }
+    };
+
     // ---- (b) collision of plane q on the tile + 1 halo (one node per thread, from cur)
     auto compute_collide = [&](int q) {
         const int sl = s4(q), slm = s4(q - 1), slp = s4(q + 1);
@@ -237,6 +255,21 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
             C fd[L::Q];
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) fd[i] = C(cur.f[i]);
+            if constexpr (RES) {
+                // force-free velocity of the stored state, FP64 (the residual's u^n)
+                double r0 = 1, j0[3] = {0, 0, 0};
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i) {
+                    const double fv = double(cur.f[i]);
+                    r0 += fv;
+#pragma unroll
+                    for (int b = 0; b < D; ++b)
+                        if (L::c[i][b]) j0[b] += L::c[i][b] * fv;
+                }
+                const double ir0 = 1.0 / r0;
+#pragma unroll
+                for (int b = 0; b < D; ++b) ru_new[b] = j0[b] * ir0;
+            }
             const Cell<L, C> c0 = mcell(sl, k2);
             Node<L, C> nd;
             nd.rho = c0.rho;
@@ -315,14 +348,14 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
                 }
                 int copies = 1;
                 bool write = true;
-                if (g.bc_x == 1) {
+                if (g.bc_x >= 1) {
                     if (INL && xu < 2) {
                         Bh[n] = S(0);
                         if (D == 3) Bh[N + n] = S(0);
                         write = false;
                     } else if (xu >= g.nx - 2) {
                         write = false;
-                    } else if (xu == g.nx - 3) {
+                    } else if (xu == g.nx - 3 && g.bc_x == 1) {
                         copies = 3;
                     }
                 }
@@ -404,6 +437,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     compute_macros(z0);
     __syncthreads();
     compute_collide(z0 - 1);
+    res_push();
     shift_planes();                                 // cur: plane z0
     __syncthreads();
     Cell<L, C> cm2 = mcell(s4(z0 - 2), k2own);
@@ -413,6 +447,7 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     compute_macros(z0 + 1);
     __syncthreads();
     compute_collide(z0);
+    res_push();
     // energy and row of the own node for its output one plane later (its forcing is prefetched)
     S ekeep = cur.e;
     int rkeep = cur.r;
@@ -435,13 +470,39 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     C pfm = 0, pfmp = 0;                            // its p + 1/2 and p - 1/2 face fluxes
     S pe = S(0);
     C pfE = 0;
+    // u^{n+1} of the pending output plane from the values stored for it (the free stream at the
+    // inlet; at the outlet copies, column nx - 3, whose rescaled copy has the same velocity)
+    auto res_acc = [&]() {
+        if constexpr (RES) {
+            if (!real) return;
+            const bool inl = INL && g.bc_x >= 1 && xo < 2;
+            double r1 = 1, j1[3] = {0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                const double fv = inl ? double(S(a.fdev[i])) : double(S(pf[i]));
+                r1 += fv;
+#pragma unroll
+                for (int b = 0; b < D; ++b)
+                    if (L::c[i][b]) j1[b] += L::c[i][b] * fv;
+            }
+            const double ir1 = 1.0 / r1;
+            double d2 = 0;
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const double d = j1[b] * ir1 - ru0[b];
+                d2 += d * d;
+            }
+            *racc += d2;
+            if (!isfinite(d2) || !isfinite(r1)) *rbad = 1;
+        }
+    };
     auto finish = [&](int q) {
         if (!real) return;
         const int fb = s2(q);
         C ediv = (sm.fex[fb][frow][jx1] - sm.fex[fb][frow][jx1 - 1]) + (pfm - pfmp);
         if constexpr (D == 3) ediv += sm.fey[fb][jy1][jx1 - 1] - sm.fey[fb][jy1 - 1][jx1 - 1];
         const long long n = gnode(xo, yo, q);
-        if (g.bc_x == 1) {
+        if (g.bc_x >= 1) {
             if (INL && xo < 2) {
 #pragma unroll
                 for (int i = 0; i < L::Q; ++i) Bf[i * N + n] = S(a.fdev[i]);
@@ -451,6 +512,8 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
             if (xo >= g.nx - 2) return;
         }
         const C enew = C(pe) - ediv + pfE;
+        if constexpr (RES)
+            if (!isfinite(double(enew))) *rbad = 1;
         if constexpr (OUT) {
             // outlet columns nx - 2, nx - 1: column nx - 3 rescaled by p_inf / p
 #pragma unroll
@@ -458,6 +521,8 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
             Be[n] = S(enew);
             if (g.bc_x == 1 && xo == g.nx - 3) {
                 const C sc = outlet_scale<L, C>(pf, enew, a.e_ref, a.eint_inf);
+                if constexpr (RES)
+                    if (!isfinite(double(sc))) *rbad = 1;
                 for (int c = 1; c < 3; ++c) {
 #pragma unroll
                     for (int i = 0; i < L::Q; ++i) Bf[i * N + n + c] = S(sc * pf[i] + (sc - C(1)) * C(L::w[i]));
@@ -479,7 +544,9 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
     for (int p = z0; p < z1; ++p) {
         compute_macros(p + 2);
         __syncthreads();
+        if (RES && p > z0) res_acc();               // plane p - 1 (ru0), before the next push
         compute_collide(p + 1);
+        res_push();
         if (p > z0) finish(p - 1);
         __syncthreads();
         // Issue the next plane's global loads now; they complete while plane p is prepared.
@@ -494,9 +561,14 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         // ---- (c) output plane p, first part
         const int fb = s2(p);
         if (own_out) {
+            // (RES: the outlet copies take the populations of column nx - 3, in the same tile, for
+            // their u^{n+1}; they store nothing themselves)
+            int sx = 0;
+            if constexpr (RES && OUT)
+                if (g.bc_x == 1 && xo >= g.nx - 2) sx = xo - (g.nx - 3);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
-                pf[i] = fcr(i, bx1 - L::c[i][0], by1 - (D == 3 ? L::c[i][1] : 0), p - cm<L>(i));
+                pf[i] = fcr(i, bx1 - sx - L::c[i][0], by1 - (D == 3 ? L::c[i][1] : 0), p - cm<L>(i));
         }
         if (own_fx) sm.fex[fb][frow][jx1] = inplane_flux(0, bx1, by1, p);
         if constexpr (D == 3) if (own_fy) sm.fey[fb][jy1][jx1 - 1] = inplane_flux(1, bx1, by1, p);
@@ -516,10 +588,11 @@ __device__ __forceinline__ void fused_tile(const FusedK<C>& a, StateP<S> A, Stat
         fm_prev = fm_now;
     }
     __syncthreads();
+    if constexpr (RES) res_acc();                   // plane z1 - 1
     finish(z1 - 1);
 }
 
-template <class L, class S, class C, int TX, int TY, int SM>
+template <class L, class S, class C, int TX, int TY, int SM, bool RES>
 __global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(FusedK<C> a, FusedArgs fa, StateP<S> A, StateP<S> B) {
     __shared__ FusedSmem<L, S, C, TX, TY> sm;
     constexpr int D = L::D;
@@ -540,19 +613,47 @@ __global__ void __launch_bounds__((TX + 2) * (L::D == 3 ? TY + 2 : 1)) k_fused(F
     // 2.4 %). Four instantiations: the common tile, inlet-only, outlet-only, and one with every
     // path, which is correct for any tile (forced tiles, small grids, a tile with both closures).
     const bool out = a.bc_x == 1 && x0 <= a.nx - 3 && a.nx - 3 <= x0 + TX - 1;
-    const bool inl = a.bc_x == 1 && x0 < 2;
+    const bool inl = a.bc_x >= 1 && x0 < 2;
     const int* fb = fa.fb;
     const bool frc = SM == 1 || (fb[0] <= fb[1] && x0 - 2 <= fb[1] && x0 + TX + 1 >= fb[0] &&
                                  (D == 2 || (y0 - 2 <= fb[3] && y0 + TY + 1 >= fb[2])) && z0 - 2 <= fb[5] &&
                                  z1 + 1 >= fb[4]);
+    double racc = 0;
+    int rbad = 0;
     if (!frc && !out && !inl)
-        fused_tile<L, S, C, TX, TY, SM, false, false, false>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
+        fused_tile<L, S, C, TX, TY, SM, false, false, false, RES>(a, A, B, x0, y0, z0, z1, SM == 1, sm, &racc, &rbad);
     else if (!frc && !out)
-        fused_tile<L, S, C, TX, TY, SM, false, false, true>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
+        fused_tile<L, S, C, TX, TY, SM, false, false, true, RES>(a, A, B, x0, y0, z0, z1, SM == 1, sm, &racc, &rbad);
     else if (!frc && !inl)
-        fused_tile<L, S, C, TX, TY, SM, true, false, false>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
+        fused_tile<L, S, C, TX, TY, SM, true, false, false, RES>(a, A, B, x0, y0, z0, z1, SM == 1, sm, &racc, &rbad);
     else
-        fused_tile<L, S, C, TX, TY, SM, true, true, true>(a, A, B, x0, y0, z0, z1, SM == 1, sm);
+        fused_tile<L, S, C, TX, TY, SM, true, true, true, RES>(a, A, B, x0, y0, z0, z1, SM == 1, sm, &racc, &rbad);
+    if constexpr (RES) {
+        // workgroup sum in a fixed order (LDS reused), one partial per logical workgroup
+        constexpr int NT = (TX + 2) * (L::D == 3 ? TY + 2 : 1);
+        static_assert(sizeof(sm) >= NT * (sizeof(double) + sizeof(int)), "reduction space");
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(&sm);
+        int* bad = reinterpret_cast<int*>(red + NT);
+        const int t = threadIdx.x;
+        red[t] = racc;
+        bad[t] = rbad;
+        __syncthreads();
+        constexpr int P2 = NT <= 64 ? 64 : (NT <= 128 ? 128 : (NT <= 256 ? 256 : (NT <= 512 ? 512 : 1024)));
+        static_assert(NT <= P2 && P2 <= 1024, "workgroup size");
+#pragma unroll
+        for (int h = P2 / 2; h > 0; h >>= 1) {
+            if (t < h && t + h < NT) {
+                red[t] += red[t + h];
+                bad[t] |= bad[t + h];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            fa.rpart[2 * logical] = red[0];
+            fa.rpart[2 * logical + 1] = bad[0] ? 1.0 : 0.0;
+        }
+    }
 }
 
 // Persistent sweep over the work items of a batch of 2D grids. The items of one case are
@@ -626,7 +727,7 @@ struct Tile<D2Q9, double> {
 
 template <class L, class S, int TX, int TY>
 hipError_t launch_fused_tile(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, int default_chunk,
-                             const int* fbox, hipStream_t st) {
+                             const int* fbox, hipStream_t st, double* rpart, int rcap, int* rparts) {
     const GridP& g = a.grid;
     FusedArgs fa;
     fa.tiles_x = (g.nx + TX - 1) / TX;
@@ -638,21 +739,30 @@ hipError_t launch_fused_tile(const SweepArgs& a, StateP<S> A, StateP<S> B, int c
     fa.per_xcd = (fa.total + 7) / 8;
     fa.small = (g.nx <= TX) || (L::D == 3 && g.ny <= TY) || nm < 4;
     for (int i = 0; i < 6; ++i) fa.fb[i] = fbox[i];
+    // The residual is formed in the sweep when every workgroup has a partial slot and the outlet
+    // copies share a tile with their source column nx - 3; otherwise the caller runs k_residual.
+    const bool res = rpart && fa.total <= rcap && (g.bc_x == 0 || (g.bc_x == 1 && (g.nx - 3) % TX <= TX - 3));
+    fa.rpart = res ? rpart : nullptr;
+    if (rparts) *rparts = res ? fa.total : 0;
     const int grid = fa.per_xcd * 8;
     constexpr int threads = (TX + 2) * (L::D == 3 ? TY + 2 : 1);
     const FusedK<S> k = fused_args<S>(a);
-    if (fa.small)
-        hipLaunchKernelGGL((k_fused<L, S, S, TX, TY, 1>), dim3(grid), dim3(threads), 0, st, k, fa, A, B);
+    if (fa.small && res)
+        hipLaunchKernelGGL((k_fused<L, S, S, TX, TY, 1, true>), dim3(grid), dim3(threads), 0, st, k, fa, A, B);
+    else if (fa.small)
+        hipLaunchKernelGGL((k_fused<L, S, S, TX, TY, 1, false>), dim3(grid), dim3(threads), 0, st, k, fa, A, B);
+    else if (res)
+        hipLaunchKernelGGL((k_fused<L, S, S, TX, TY, 0, true>), dim3(grid), dim3(threads), 0, st, k, fa, A, B);
     else
-        hipLaunchKernelGGL((k_fused<L, S, S, TX, TY, 0>), dim3(grid), dim3(threads), 0, st, k, fa, A, B);
+        hipLaunchKernelGGL((k_fused<L, S, S, TX, TY, 0, false>), dim3(grid), dim3(threads), 0, st, k, fa, A, B);
     return hipGetLastError();
 }
 
 template <class L, class S>
 hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, const int* fbox,
-                             hipStream_t st) {
+                             hipStream_t st, double* rpart, int rcap, int* rparts) {
     using TL = Tile<L, S>;
-    return launch_fused_tile<L, S, TL::TX, TL::TY>(a, A, B, chunk, TL::CHUNK, fbox, st);
+    return launch_fused_tile<L, S, TL::TX, TL::TY>(a, A, B, chunk, TL::CHUNK, fbox, st, rpart, rcap, rparts);
 }
 
 template <class L, class S>
@@ -691,9 +801,13 @@ template hipError_t launch_fused_batch<D2Q9, double>(const CaseDesc<double>*, in
 template int fused_batch_occupancy<D2Q9, float>(int);
 template int fused_batch_occupancy<D2Q9, double>(int);
 
-template hipError_t launch_fused_step<D2Q9, float>(const SweepArgs&, StateP<float>, StateP<float>, int, const int*, hipStream_t);
-template hipError_t launch_fused_step<D2Q9, double>(const SweepArgs&, StateP<double>, StateP<double>, int, const int*, hipStream_t);
-template hipError_t launch_fused_step<D3Q19, float>(const SweepArgs&, StateP<float>, StateP<float>, int, const int*, hipStream_t);
-template hipError_t launch_fused_step<D3Q19, double>(const SweepArgs&, StateP<double>, StateP<double>, int, const int*, hipStream_t);
+template hipError_t launch_fused_step<D2Q9, float>(const SweepArgs&, StateP<float>, StateP<float>, int, const int*, hipStream_t,
+                                                  double*, int, int*);
+template hipError_t launch_fused_step<D2Q9, double>(const SweepArgs&, StateP<double>, StateP<double>, int, const int*, hipStream_t,
+                                                  double*, int, int*);
+template hipError_t launch_fused_step<D3Q19, float>(const SweepArgs&, StateP<float>, StateP<float>, int, const int*, hipStream_t,
+                                                  double*, int, int*);
+template hipError_t launch_fused_step<D3Q19, double>(const SweepArgs&, StateP<double>, StateP<double>, int, const int*, hipStream_t,
+                                                  double*, int, int*);
 
 }  // namespace lbmib

@@ -163,14 +163,14 @@ __global__ void __launch_bounds__(TPB) k_collide(SweepArgs a, StateP<S> A, State
     }
     // New diagonal history into B, with the closure of the x boundaries.
     int copies = 1;
-    if (g.bc_x == 1) {
+    if (g.bc_x >= 1) {
         if (x < 2) {
             B.h2[n] = S(0);
             if (D == 3) B.h2[N + n] = S(0);
             return;
         }
         if (x >= g.nx - 2) return;
-        if (x == g.nx - 3) copies = 3;
+        if (x == g.nx - 3 && g.bc_x == 1) copies = 3;
     }
     for (int k = 0; k < copies; ++k) {
         B.h2[n + k] = S(H2n[0][0]);
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(TPB)
     constexpr int D = L::D;
     int x, y, z;
     decode(g, n, x, y, z);
-    if (g.bc_x == 1) {
+    if (g.bc_x >= 1) {
         if (x < 2) {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) B.f[i * N + n] = S(a.fs.fdev[i]);
@@ -491,16 +491,25 @@ hipError_t launch_import(const SweepArgs& a, StateP<S> A, int c, const double* i
     hipLaunchKernelGGL((k_import<L, S>), dim3(blocks_for(a.grid.N)), dim3(TPB), 0, st, a, A, c, in, bad);
     return hipGetLastError();
 }
-template <class L, class S>
-hipError_t launch_residual(const SweepArgs& a, StateP<S> Old, StateP<S> New, double* partials, int nparts,
-                           double* out, hipStream_t st) {
-    hipLaunchKernelGGL((k_residual<L, S>), dim3(nparts), dim3(TPB), 0, st, a, Old, New, partials);
+template <class L>
+hipError_t launch_residual_final(const SweepArgs& a, const double* partials, int nparts, double* out, hipStream_t st) {
     double ur = 0;
     for (int b = 0; b < L::D; ++b) ur += a.fs.u_inf[b] * a.fs.u_inf[b];
     ur = sqrt(ur);
     const double scale = ur > 0 ? 1.0 / (ur * sqrt((double)a.grid.N)) : 1.0 / sqrt((double)a.grid.N);
-    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(TPB), 0, st, (const double*)partials, nparts, scale, out);
+    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(TPB), 0, st, partials, nparts, scale, out);
     return hipGetLastError();
+}
+template hipError_t launch_residual_final<D2Q9>(const SweepArgs&, const double*, int, double*, hipStream_t);
+template hipError_t launch_residual_final<D3Q19>(const SweepArgs&, const double*, int, double*, hipStream_t);
+
+template <class L, class S>
+hipError_t launch_residual(const SweepArgs& a, StateP<S> Old, StateP<S> New, double* partials, int nparts,
+                           double* out, hipStream_t st) {
+    hipLaunchKernelGGL((k_residual<L, S>), dim3(nparts), dim3(TPB), 0, st, a, Old, New, partials);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_residual_final<L>(a, partials, nparts, out, st);
 }
 
 #define LBMIB_INST_S(L, S)                                                                                     \

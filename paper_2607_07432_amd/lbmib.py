@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, 'liblbmib.so')
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_STATE, LBM_E_NONFINITE = 0, -1, -2, -3, -4, -5
 F32, F64 = 32, 64
 SWEEP_FUSED, SWEEP_THREE_PASS = 0, 1
-BC_PERIODIC, BC_INFLOW_OUTFLOW = 0, 1
+BC_PERIODIC, BC_INFLOW_OUTFLOW, BC_CHARACTERISTIC = 0, 1, 2
 
 EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step', 'lbm_step_timed',
            'ib_wall_loads', 'ib_wall_loads_noalloc', 'lbm_fields',
@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
                 ('gamma', ctypes.c_double), ('mu', ctypes.c_double), ('lambda_', ctypes.c_double),
                 ('sigma', ctypes.c_double), ('rho_inf', ctypes.c_double), ('u_inf', ctypes.c_double * 3),
                 ('T_inf', ctypes.c_double), ('ref_len', ctypes.c_double), ('ref_area', ctypes.c_double),
-                ('surface', ctypes.c_double), ('T_wall', ctypes.c_double)]
+                ('surface', ctypes.c_double), ('T_wall', ctypes.c_double), ('sigma_c', ctypes.c_double)]
 
 
 class Loads(ctypes.Structure):
@@ -153,7 +153,8 @@ def params_from_case(case, precision=F64, max_markers=None, with_aC=True, sweep=
     p.nx, p.ny = case.dims[0], case.dims[1]
     p.nz = case.dims[2] if case.dim == 3 else 1
     p.precision = precision
-    p.bc_x = BC_INFLOW_OUTFLOW if case.bc == 'inflow_outflow' else BC_PERIODIC
+    p.bc_x = {'inflow_outflow': BC_INFLOW_OUTFLOW, 'characteristic': BC_CHARACTERISTIC}.get(case.bc, BC_PERIODIC)
+    p.sigma_c = getattr(case, 'sigma_c', 0.25)
     p.kernel = case.kernel
     m = len(case.X) if case.X is not None else 0
     p.max_markers = max_markers if max_markers is not None else max(m, 1)

@@ -151,7 +151,8 @@ class Case:
     rho_inf: float = 1.0
     gamma: float = GAMMA
     sigma: float = 0.98
-    bc: str = 'inflow_outflow'
+    bc: str = 'inflow_outflow'          # 'periodic', 'inflow_outflow' or 'characteristic' (x closure)
+    sigma_c: float = 0.25               # characteristic outlet: relaxation of the incoming wave
     X: np.ndarray = None
     n: np.ndarray = None
     u_wall: np.ndarray = None
@@ -295,6 +296,27 @@ def precision_case(nx=512, ny=256, nz=256, center=None):
     T_w = 1.2 T_inf, Ma 0.2, Re 300 (the recipe's Ma 0.5 / T_w = 1.5 T_inf diverges within 50
     steps from the impulsive start in this scheme, on the oracle as on the GPU)."""
     return sphere_case(nx=nx, ny=ny, nz=nz, center=center, mach=0.2, reynolds=300.0, T_wall_ratio=1.2)
+
+
+def acoustic_pulse(nx=160, ny=4, u_inf=0.1, amp=1e-3, x0=60.0, width=6.0, mu=0.005, bc='characteristic',
+                   sigma_c=0.0):
+    """A plane right-running isentropic pressure pulse on a stream along x (2D, no body, periodic
+    in y): p' = amp exp(-(x - x0)^2 / (2 width^2)), u' = p'/(rho c), rho' = p'/c^2 about
+    (rho, T) = (1, 1), c^2 = gamma R T. Returns the case and its fields rho [ny, nx],
+    u [2, ny, nx], T [ny, nx]; it tests how much of an outgoing wave an outlet closure reflects."""
+    c = math.sqrt(GAMMA * R_GAS)
+    x = np.arange(nx, dtype=np.float64)
+    dp = amp * np.exp(-0.5 * ((x - x0) / width) ** 2)
+    rho1 = 1.0 + dp / c ** 2
+    u1 = u_inf + dp / c
+    T1 = (R_GAS + dp) / (rho1 * R_GAS)
+    lam = mu * (GAMMA * R_GAS / (GAMMA - 1.0)) / PRANDTL
+    case = Case(name='pulse', dim=2, dims=(nx, ny), mu=mu, lam=lam, u_inf=(u_inf, 0.0), T_inf=1.0, bc=bc,
+                sigma_c=sigma_c, ref_len=1.0, steps=1)
+    rho = np.tile(rho1, (ny, 1))
+    u = np.stack([np.tile(u1, (ny, 1)), np.zeros((ny, nx))])
+    T = np.tile(T1, (ny, 1))
+    return case, rho, u, T
 
 
 def conduction_number(case):

@@ -10,7 +10,7 @@ from paper_2607_07432_amd import workloads as wl
 def oracle_params(case, with_aC=True):
     u = tuple(case.u_inf) + (0.0,) * (3 - len(case.u_inf))
     return olbm.Params(mu=case.mu, lam=case.lam, gamma=case.gamma, sigma=case.sigma, rho_inf=case.rho_inf,
-                       u_inf=u[:case.dim], T_inf=case.T_inf, bc=case.bc, with_aC=with_aC)
+                       u_inf=u[:case.dim], T_inf=case.T_inf, bc=case.bc, with_aC=with_aC, sigma_c=case.sigma_c)
 
 
 def oracle_geometry(case):

@@ -54,7 +54,15 @@ CASES = {
     'sph_R_rot': lambda: small_sphere_case(omega_star=0.6),
     # non-convex body: 5-point star of Eq. (39)
     'star_R': lambda: wl.star_case(48, 0.1, 0.3, 0.15, 30.0, nx=72, ny=48, steps=1),
+    # characteristic outlet (relaxation sigma_c = 0.25)
+    'cyl_R_char': lambda: cylinder_small(bc='characteristic'),
+    'sph_R_char': lambda: _with_bc(small_sphere_case(), 'characteristic'),
 }
+
+
+def _with_bc(c, bc):
+    c.bc = bc
+    return c
 
 
 def _periodic(c):
@@ -132,7 +140,8 @@ def test_one_step_fp64_parity(lbmib, name, sweep):
 
 
 @pytest.mark.parametrize('sweep', list(SWEEPS))
-@pytest.mark.parametrize('name', ['cyl_R_io', 'sph_R_iso', 'cyl_R_rot', 'cyl_F_rot_adiabatic', 'sph_R_rot'])
+@pytest.mark.parametrize('name', ['cyl_R_io', 'sph_R_iso', 'cyl_R_rot', 'cyl_F_rot_adiabatic', 'sph_R_rot', 'cyl_R_char',
+                                  'sph_R_char'])
 def test_multi_step_fp64_parity_and_loads(lbmib, name, sweep):
     case = CASES[name]()
     lat = for_dim(case.dim)
