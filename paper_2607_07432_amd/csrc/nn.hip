@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -357,6 +358,153 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_lds(const __bf16* __restrict
             bpart[(long long)s * cout + co0 + t] = v;
         }
     }
+}
+
+// Weight and bias gradients, deeper steps: as k_conv_wgrad_lds, but each barrier pair covers KP
+// pixels (KP / 32 MFMA steps per 16 x 16 sub-tile) and every thread stages several 8-channel
+// vectors of each operand. Requires W % KP == 0 and splits of a multiple of KP pixels. The bias gradient (row sums of dY over the pixels) comes from the
+// same MFMA unit: the wavefronts of the first k tile multiply their dY rows by a ones operand.
+template <int BM, int KP>
+__global__ void __launch_bounds__(256) k_conv_wgrad_deep(const __bf16* __restrict__ dY, int cout, int dys,
+                                                         const __bf16* __restrict__ X, int cin, int xs, int taps, int H,
+                                                         int Wd, long long P, int split_len, int nsplit,
+                                                         float* __restrict__ part, float* __restrict__ bpart) {
+    constexpr int BN = 4096 / BM;
+    constexpr int LD = KP + 8;
+    constexpr int AV = BM * KP / 8, BV = BN * KP / 8;      // 8-channel vectors per step
+    constexpr int AR = (AV + 255) / 256, BR = (BV + 255) / 256;
+    __shared__ __bf16 As[BM][LD];
+    __shared__ __bf16 Bs[BN][LD];
+    const int K = taps * cin;
+    const int co_tiles = cout / BM, k_tiles = (K + BN - 1) / BN;
+    const int b = blockIdx.x;
+    const int cot = b % co_tiles, kt = (b / co_tiles) % k_tiles, s = b / (co_tiles * k_tiles);
+    if (s >= nsplit) return;
+    const int co0 = cot * BM, k0 = kt * BN;
+    const int t = threadIdx.x, lane = t % WAVE, wv = t / WAVE;
+    constexpr int WN = BN / 32;                    // wavefronts along k
+    const int wm = wv / WN, wn = wv % WN;
+    const int HW = H * Wd;
+    const long long pbeg = (long long)s * split_len;
+    const long long pend = pbeg + split_len < P ? pbeg + split_len : P;
+    const bool bias = kt == 0 && wn == 0;
+    f32x4 acc[2][2], accb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const bf16x8 zero = {};
+    bf16x8 ones;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
+    // A step of KP pixels starts at a multiple of KP and W is a multiple of KP: its pixels share
+    // the image and the row, so only the step's base is divided; the channel offsets, taps and
+    // shifts of each staged vector are fixed for the whole split.
+    int b_ci[BR], b_dy[BR], b_dx[BR], b_pix[BR];
+    bool b_on[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+        const int v_ = t + 256 * r;
+        const int g = v_ / KP, k = k0 + 8 * g;
+        b_pix[r] = v_ % KP;
+        b_on[r] = v_ < BV && k < K;
+        const int tap = k / cin;
+        b_ci[r] = k - tap * cin;
+        b_dy[r] = taps == 9 ? tap / 3 - 1 : 0;
+        b_dx[r] = taps == 9 ? tap % 3 - 1 : 0;
+    }
+    bf16x8 va[AR], vb[BR];
+    auto load = [&](long long q) {
+        const long long n = q / HW;
+        const int rr = (int)(q - n * HW);
+        const int y0 = rr / Wd, x0 = rr - y0 * Wd;
+#pragma unroll
+        for (int r = 0; r < AR; ++r) {
+            const int v_ = t + 256 * r;
+            va[r] = zero;
+            if (v_ < AV) {
+                const int pix = v_ % KP, g = v_ / KP;
+                const long long p = q + pix;
+                if (p < pend) va[r] = *reinterpret_cast<const bf16x8*>(dY + p * dys + co0 + 8 * g);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            vb[r] = zero;
+            if (b_on[r] && q + b_pix[r] < pend) {
+                const int y = y0 + b_dy[r], x = x0 + b_pix[r] + b_dx[r];
+                if (y >= 0 && y < H && x >= 0 && x < Wd)
+                    vb[r] = *reinterpret_cast<const bf16x8*>(X + (n * HW + (long long)y * Wd + x) * xs + b_ci[r]);
+            }
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int r = 0; r < AR; ++r) {
+            const int v_ = t + 256 * r;
+            if (v_ < AV) {
+                const int pix = v_ % KP, g = v_ / KP;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) As[8 * g + e][pix] = va[r][e];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            const int v_ = t + 256 * r;
+            if (v_ < BV) {
+                const int pix = v_ % KP, g = v_ / KP;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) Bs[8 * g + e][pix] = vb[r][e];
+            }
+        }
+    };
+    if (pbeg < pend) load(pbeg);
+    for (long long q = pbeg; q < pend; q += KP) {
+        store();
+        __syncthreads();
+        if (q + KP < pend) load(q + KP);
+#pragma unroll
+        for (int ks = 0; ks < KP / 32; ++ks) {
+            bf16x8 a[2], bb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + i * 16 + lane % 16][32 * ks + 8 * (lane / 16)]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                bb[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + j * 16 + lane % 16][32 * ks + 8 * (lane / 16)]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
+            if (bias)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], ones, accb[i], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float* out = part + (long long)s * cout * K;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int k = k0 + wn * 32 + j * 16 + lane % 16;
+            if (k >= K) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = co0 + wm * 32 + i * 16 + (lane / 16) * 4 + r;
+                out[(long long)co * K + k] = acc[i][j][r];
+            }
+        }
+    // every column of the ones product holds the row sums; column 0 is written
+    if (bias && lane % 16 == 0)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                bpart[(long long)s * cout + co0 + wm * 32 + i * 16 + (lane / 16) * 4 + r] = accb[i][r];
 }
 
 // Fixed-order sum of the split partials into the FP32 gradient.
@@ -923,6 +1071,18 @@ hipError_t conv_fwd(nn_unet* u, const Layer& ly, const __bf16* X, int xstride, c
     return hipGetLastError();
 }
 
+// Pixels per staging step of the weight gradient: 128 when the image width is a multiple of 128
+// and each split keeps at least two such steps (LBMIB_WGRAD_KP=32 selects the shallow kernel,
+// for comparison), else 32.
+int wgrad_kp(long long P, long long nsplit, int W) {
+    static const int forced = [] {
+        const char* v = std::getenv("LBMIB_WGRAD_KP");
+        return v ? std::atoi(v) : 0;
+    }();
+    if (forced == 32) return 32;
+    return (W % 128 == 0 && P / nsplit >= 256) ? 128 : 32;
+}
+
 // dW (into grad at w_off) and db (at b_off) of a 3x3 layer from dY [P] (stride dys) and its input X.
 hipError_t conv_wgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, const __bf16* X, int xs, int B, int H,
                       int W) {
@@ -938,11 +1098,19 @@ hipError_t conv_wgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, co
     nsplit = std::min<long long>(nsplit, 256);
     while ((size_t)nsplit * wsz > u->split_floats && nsplit > 1) --nsplit;
     while ((size_t)nsplit * ly.cout > u->small_floats && nsplit > 1) --nsplit;
+    // deeper steps (KP pixels per barrier pair) while every split still holds two of them
+    const int KP = wgrad_kp(P, nsplit, W);
     long long split_len = (P + nsplit - 1) / nsplit;
-    split_len = (split_len + 31) / 32 * 32;
+    split_len = (split_len + KP - 1) / KP * KP;
     nsplit = (P + split_len - 1) / split_len;
     const dim3 grid((unsigned)(tiles * nsplit));
-    if (BM == 64)
+    if (KP == 128 && BM == 64)
+        hipLaunchKernelGGL((k_conv_wgrad_deep<64, 128>), grid, dim3(256), 0, u->stream, dY, ly.cout, dys, X, ly.cin, xs,
+                           ly.taps, H, W, P, (int)split_len, (int)nsplit, u->split, u->small);
+    else if (KP == 128)
+        hipLaunchKernelGGL((k_conv_wgrad_deep<32, 128>), grid, dim3(256), 0, u->stream, dY, ly.cout, dys, X, ly.cin, xs,
+                           ly.taps, H, W, P, (int)split_len, (int)nsplit, u->split, u->small);
+    else if (BM == 64)
         hipLaunchKernelGGL(k_conv_wgrad_lds<64>, grid, dim3(256), 0, u->stream, dY, ly.cout, dys, X, ly.cin, xs, ly.taps,
                            H, W, P, (int)split_len, (int)nsplit, u->split, u->small);
     else
