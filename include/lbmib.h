@@ -118,15 +118,17 @@ int lbm_init_grid(const lbm_params* p, void* dev_workspace, size_t bytes, void* 
  * X* of Eq. (25), d_BV, projection points, W of Eq. (17), node -> marker CSR) and uploads it.
  * Replaces any previous body and clears the force history held at forced nodes.
  * Errors: LBM_E_INVAL (non-finite input, |n| != 1 within 1e-12, a marker within 4 cells of an
- * x boundary under the inflow/outflow closure or within 3 cells of any edge, m > max_markers),
+ * x boundary under the inflow/outflow or characteristic closure or within 3 cells of any edge, m > max_markers),
  * LBM_E_NOMEM (precomputed lists exceed the workspace), LBM_E_HIP. m = 0 removes the body. */
 int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal,
                    const double* area_w, const double* u_wall, const int* t_kind,
                    const double* t_value, int method);
 
-/* Enqueue n time steps on the handle's stream. Asynchronous; the last step also accumulates
- * the FP64 velocity residual r = ||u^{n+1} - u^n|| / (|u_inf| sqrt(N)) and a non-finite check
- * (read with lbm_residual). Errors: LBM_E_INVAL (n < 0), LBM_E_HIP. */
+/* Enqueue n time steps on the handle's stream (Sec. 2.5). Asynchronous; the last step also
+ * accumulates the FP64 velocity residual r = ||u^{n+1} - u^n|| / (|u_inf| sqrt(N)) over the
+ * stored states and a non-finite check (read with lbm_residual): inside the fused sweep, or by a
+ * separate pass for the three-pass sweep and the characteristic outlet. Errors: LBM_E_INVAL
+ * (n < 0), LBM_E_HIP. */
 int lbm_step(lbm_handle* h, int n);
 
 /* As lbm_step, and also times the launches of every step with HIP events recorded on the
