@@ -144,6 +144,28 @@ MUTATIONS = [
     ('lbm.py', 'c = np.sqrt(prm.gamma * pp / r)', 'c = np.sqrt(pp / r)',
      T + 'test_oracle_outlet.py::test_characteristic_outlet_absorbs_an_acoustic_pulse',
      'isothermal instead of adiabatic sound speed at the outlet'),
+    ('refine.py', 'lambda rho: _taubar(prm_f, rho) / (2.0 * _taubar(prm_c, rho))', 'lambda rho: 1.0 + 0.0 * rho',
+     T + 'test_oracle_refine.py::test_shear_wave_crosses_the_block',
+     'non-equilibrium populations not rescaled from coarse to fine'),
+    ('refine.py', 'mu=2.0 * prm_c.mu, lam=2.0 * prm_c.lam', 'mu=prm_c.mu, lam=prm_c.lam',
+     T + 'test_oracle_refine.py::test_shear_wave_crosses_the_block', 'fine viscosity not doubled in lattice units'),
+    ('refine.py', 'fill_band(lat, prm_c, prm_f, st, st_c, new_c, 0.5 * k, block)',
+     'fill_band(lat, prm_c, prm_f, st, st_c, new_c, 1.0, block)',
+     T + 'test_oracle_refine.py::test_acoustic_pulse_crosses_the_block', 'no time interpolation of the band'),
+    ('refine.py', 'frac.append((xf % 2) * 0.5)', 'frac.append((xf % 2) * 0.0)',
+     T + 'test_oracle_refine.py::test_acoustic_pulse_crosses_the_block', 'no spatial interpolation of the band'),
+    ('refine.py', 'hi.append((i0 + 1) % nc)', 'hi.append((i0 - 1) % nc)',
+     T + 'test_oracle_refine.py::test_interpolation_reproduces_multilinear_fields', 'interpolation neighbour'),
+    ('refine.py', 'lambda rho: 2.0 * _taubar(prm_c, rho) / _taubar(prm_f, rho)',
+     'lambda rho: _taubar(prm_f, rho) / (2.0 * _taubar(prm_c, rho))',
+     T + 'test_oracle_refine.py::test_transfer_there_and_back_is_the_identity',
+     'restriction scales the non-equilibrium part like the prolongation'),
+    ('refine.py', 'H2d = 0.5 * np.stack', 'H2d = 1.0 * np.stack',
+     T + 'test_oracle_refine.py::test_transfer_there_and_back_is_the_identity', 'force history not halved on the fine level'),
+    ('refine.py', '((x < G) | (x >= n - G))', '((x < G) | (x > n - G))',
+     T + 'test_oracle_refine.py::test_band_and_restriction_sets', 'band one node short at the upper edges'),
+    ('refine.py', 'i = i[(i >= block.R) & (i <= n - 1 - block.R)]', 'i = i[(i > block.R) & (i <= n - 1 - block.R)]',
+     T + 'test_oracle_refine.py::test_band_and_restriction_sets', 'restriction margin off by one'),
 ]
 
 
