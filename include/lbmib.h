@@ -243,6 +243,58 @@ void lbm_batch_destroy(lbm_batch* b);
 /* Message of the last error of this batch (of the last failed lbm_batch_create if b is NULL). */
 const char* lbm_batch_last_error(lbm_batch* b);
 
+/* ---- Two-level grid refinement ---------------------------------------------------------------
+ * The paper computes every case on locally refined meshes without stating the scheme; this pair
+ * of handles is the one adopted here (ratio 2, acoustic scaling). A fine handle covers a block of
+ * the coarse grid: fine node 2k on axis a coincides with coarse node origin[a] + k, so the block
+ * spans nf_a / 2 coarse cells. Lattice velocities, density and temperature are shared; the fine
+ * handle is created with twice the coarse mu and lambda_ (lattice units of half the spacing and
+ * half the step) and periodic closure (its edges are overwritten). One coupled step:
+ *   1. the coarse grid takes one step (lbm_step);
+ *   2. the fine grid takes two steps; after each, its outer band of `band` nodes is refilled from
+ *      the coarse grid: coarse values linear in time (weight 1/2, then 1) between the states before
+ *      and after step 1, multilinear in space;
+ *   3. every coarse node whose fine counterpart lies at least `margin` fine nodes inside the block
+ *      on every axis takes the fine values (restriction).
+ * A transferred population keeps the equilibrium of its own density, velocity and temperature
+ * (Eq. (A.3)) and scales its non-equilibrium part by s = taubar_f / (2 taubar_c) coarse to fine and
+ * 1/s fine to coarse, taubar = mu / (rho cs^2) + 1/2 of each level (Eq. (6)); rho E is transferred
+ * unchanged; the diagonal force history (a per-step quantity) by 1/2 and 2. The off-diagonal force
+ * history exists only at a level's own forced nodes and is not transferred. The coupling is not
+ * conservative. All arithmetic of the transfers is FP64; the stored state keeps each handle's
+ * precision. Kernels run on the handles' common stream; no device memory is allocated.
+ * Requirements (checked at creation, and the body ones before every step):
+ *   - both handles of one dimension, precision, device and stream; equal gamma, sigma, rho_inf,
+ *     u_inf, T_inf, with_aC; fine mu and lambda_ twice the coarse ones (relative 1e-12);
+ *   - fine bc_x = LBM_BC_PERIODIC; fine node counts even, each > 2 band; 2 <= band <= margin;
+ *   - the block inside the coarse grid without wrapping (origin[a] >= 0, origin[a] + nf_a / 2 <=
+ *     nc_a - 1), and along x clear of the closure columns when the coarse bc_x is not periodic
+ *     (origin[0] >= 2, origin[0] + nf_x / 2 <= nx_c - 3);
+ *   - no body on the coarse handle; the fine body's forced nodes at least `margin` nodes from
+ *     every edge of the fine grid. */
+typedef struct lbm_refine lbm_refine;
+
+/* Couple two handles; origin[dim] in coarse nodes. The handles outlive the coupling.
+ * Errors: LBM_E_INVAL (see requirements), LBM_E_NOMEM (host). */
+int lbm_refine_create(lbm_handle* coarse, lbm_handle* fine, const int* origin, int band, int margin,
+                      lbm_refine** out);
+
+/* Set every fine node from the current coarse state (interpolated and rescaled as the band),
+ * with zero off-diagonal force history; the coarse state is not changed. Asynchronous.
+ * Errors: LBM_E_INVAL, LBM_E_HIP. */
+int lbm_refine_prolong(lbm_refine* r);
+
+/* Enqueue n coupled steps. The last one leaves in the coarse handle the residual (lbm_residual)
+ * between the coarse states before and after it, restriction included. Asynchronous.
+ * Errors: LBM_E_INVAL (n < 0, a body requirement broken), LBM_E_HIP. */
+int lbm_refine_step(lbm_refine* r, int n);
+
+/* Release the coupling (not the handles). */
+void lbm_refine_destroy(lbm_refine* r);
+
+/* Message of the last error of this coupling (of the last failed lbm_refine_create if r is NULL). */
+const char* lbm_refine_last_error(lbm_refine* r);
+
 /* ---- Learned warm start helpers (2D handles; the network is declared in lbmib_nn.h) --------
  * Ma = |u_inf| / sqrt(gamma R T_inf). Arrays are device FP32 [N][4], node = x + nx y. */
 

@@ -20,7 +20,7 @@ ARCH = 'gfx950'
 HIP_FLAGS = ['-O3', '-std=c++17', '-fPIC', f'--offload-arch={ARCH}', '-munsafe-fp-atomics',
              '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops', '-Wno-unused-result']
 HOST_FLAGS = ['-O2', '-std=c++17', '-fPIC', '-ffp-contract=off']
-HIP_SOURCES = ['sweep_split.hip', 'sweep_fused.hip', 'outlet.hip', 'ib.hip', 'api.hip', 'batch.hip', 'nn.hip', 'learn.hip']
+HIP_SOURCES = ['sweep_split.hip', 'sweep_fused.hip', 'outlet.hip', 'refine.hip', 'ib.hip', 'api.hip', 'batch.hip', 'nn.hip', 'learn.hip']
 HOST_SOURCES = ['precompute.cpp']
 
 

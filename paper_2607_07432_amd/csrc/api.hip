@@ -430,10 +430,11 @@ int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal, 
 
 namespace {
 
-// n steps; with ev (4 events per step) the marker, spread and sweep launches are bracketed.
-int run_steps(lbm_handle* h, int n, hipEvent_t* ev) {
+// n steps; with ev (4 events per step) the marker, spread and sweep launches are bracketed. The
+// last step forms the residual unless want_resid is false.
+int run_steps(lbm_handle* h, int n, hipEvent_t* ev, bool want_resid = true) {
     for (int s = 0; s < n; ++s) {
-        const bool last = s == n - 1;
+        const bool last = want_resid && s == n - 1;
         hipEvent_t* e4 = ev ? ev + 4 * s : nullptr;
         hipError_t e = dispatch(h, [&](auto L, auto S) {
             using LT = decltype(L);
@@ -787,3 +788,16 @@ int lbm_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
 const char* lbm_last_error(lbm_handle* h) { return h ? h->err.c_str() : g_init_error.c_str(); }
 
 }  // extern "C"
+
+int lbmib::step_handle(lbm_handle* h, int n, bool want_resid) { return run_steps(h, n, nullptr, want_resid); }
+
+int lbmib::residual_handle(lbm_handle* h) {
+    hipError_t e = dispatch(h, [&](auto L, auto S) {
+        using LT = decltype(L);
+        using ST = decltype(S);
+        return launch_residual<LT, ST>(h->args, other<ST>(h), current<ST>(h), h->d.partials, residual_parts(h->N),
+                                       h->d.resid, h->stream);
+    });
+    if (e != hipSuccess) return fail(h, LBM_E_HIP, std::string("residual: ") + hipGetErrorString(e));
+    return LBM_OK;
+}

@@ -72,4 +72,10 @@ StateP<S> stateB(lbm_handle* h) {
 // Recompute the kernel argument blocks of a handle from its current state index and body.
 void refresh_handle_args(lbm_handle* h);
 
+// n steps of one handle as lbm_step; the last one forms the residual only if want_resid.
+int step_handle(lbm_handle* h, int n, bool want_resid);
+
+// The residual between the previous and the current state (as lbm_residual reports it), enqueued.
+int residual_handle(lbm_handle* h);
+
 }  // namespace lbmib

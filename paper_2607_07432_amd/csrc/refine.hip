@@ -1,0 +1,387 @@
+// Two-level grid refinement (ratio 2): a fine handle embedded in a coarse one, coupled by a band
+// refilled from the coarse grid and by restriction of the fine block (contract in include/lbmib.h).
+//
+// Both transfers are gathers with one thread per destination node, FP64 arithmetic whatever the
+// storage precision. A band node reads 2^D coarse nodes of two states (time interpolation); a
+// restricted coarse node reads one fine node. Their traffic is a few per cent of the fine sweeps'.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <string>
+
+#include "handle.hpp"
+
+namespace lbmib {
+namespace {
+
+constexpr int RTPB = 256;
+
+struct RefineGeom {
+    int nc[3];          // coarse nodes per axis (x, y, z; 1 past the dimension)
+    int nf[3];          // fine nodes per axis
+    int org[3];         // coarse node of fine node 0
+    int G;              // band width (fine nodes)
+    long long Nc, Nf;   // nodes per grid
+    long long nband;    // band nodes
+    int rlo[3], rn[3];  // restriction: first fine index (even) and number of restricted nodes per axis
+    long long nrest;
+};
+
+struct RefineGas {
+    double mu_c, mu_f;  // viscosities of the two levels (lattice units)
+    double inv_Cv;
+    double e_ref;       // reference of the stored energy deviation (equal on both levels)
+};
+
+__device__ __forceinline__ double taubar_of(double mu, double rho) { return mu * 3.0 / rho + 0.5; }
+
+// Fine coordinates of band node k: in 3D the z slabs first, then, plane by plane, the y rows and the
+// x columns of the ring of one plane.
+template <int D>
+__device__ __forceinline__ void band_node(const RefineGeom& g, long long k, int* x) {
+    const int nx = g.nf[0], ny = g.nf[1], nz = g.nf[2], G = g.G;
+    x[2] = 0;
+    if (D == 3) {
+        const long long slab = (long long)2 * G * nx * ny;
+        if (k < slab) {
+            const int zi = (int)(k / ((long long)nx * ny));
+            const long long r = k % ((long long)nx * ny);
+            x[2] = zi < G ? zi : nz - 2 * G + zi;
+            x[1] = (int)(r / nx);
+            x[0] = (int)(r % nx);
+            return;
+        }
+        k -= slab;
+        const long long ring = (long long)nx * ny - (long long)(nx - 2 * G) * (ny - 2 * G);
+        x[2] = G + (int)(k / ring);
+        k %= ring;
+    }
+    const long long rows = (long long)2 * G * nx;
+    if (k < rows) {
+        const int yi = (int)(k / nx);
+        x[1] = yi < G ? yi : ny - 2 * G + yi;
+        x[0] = (int)(k % nx);
+        return;
+    }
+    k -= rows;
+    x[1] = G + (int)(k / (2 * G));
+    const int c = (int)(k % (2 * G));
+    x[0] = c < G ? c : nx - 2 * G + c;
+}
+
+// Populations f~ (deviations), e and h2 interpolated at fine node x from the coarse states
+// (1 - wt) A + wt B (multilinear in space), then rescaled to the fine level and stored.
+template <class L, class S, bool ALL>
+__global__ void __launch_bounds__(RTPB) k_refine_prolong(RefineGeom g, RefineGas q, StateP<S> A, StateP<S> B,
+                                                         double wt, StateP<S> F) {
+    constexpr int D = L::D, Q = L::Q;
+    const long long k = (long long)blockIdx.x * RTPB + threadIdx.x;
+    int x[3] = {0, 0, 0};
+    if (ALL) {
+        if (k >= g.Nf) return;
+        x[0] = (int)(k % g.nf[0]);
+        const long long r = k / g.nf[0];
+        x[1] = (int)(r % g.nf[1]);
+        x[2] = (int)(r / g.nf[1]);
+    } else {
+        if (k >= g.nband) return;
+        band_node<D>(g, k, x);
+    }
+    int i0[3];
+    double fr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        i0[a] = a < D ? g.org[a] + (x[a] >> 1) : 0;
+        fr[a] = a < D ? 0.5 * (x[a] & 1) : 0.0;
+    }
+    double fd[Q], e = 0.0, h[D - 1];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fd[i] = 0.0;
+#pragma unroll
+    for (int c = 0; c < D - 1; ++c) h[c] = 0.0;
+    const double wa = 1.0 - wt;
+    // corners in the order (x bit, y bit[, z bit]) with the x bit slowest
+#pragma unroll
+    for (int cb = 0; cb < (1 << D); ++cb) {
+        double w = 1.0;
+        int ci[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int bit = (cb >> (D - 1 - a)) & 1;
+            w *= bit ? fr[a] : 1.0 - fr[a];
+            ci[a] = i0[a] + bit;
+        }
+        if (w == 0.0) continue;
+        const long long n = ci[0] + (long long)g.nc[0] * (ci[1] + (long long)g.nc[1] * ci[2]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            fd[i] += w * (wa * double(A.f[(long long)i * g.Nc + n]) + wt * double(B.f[(long long)i * g.Nc + n]));
+        e += w * (wa * double(A.e[n]) + wt * double(B.e[n]));
+#pragma unroll
+        for (int c = 0; c < D - 1; ++c)
+            h[c] += w * (wa * double(A.h2[(long long)c * g.Nc + n]) + wt * double(B.h2[(long long)c * g.Nc + n]));
+    }
+    double rho = 1.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rho += fd[i];
+#pragma unroll
+        for (int a = 0; a < D; ++a) j[a] += double(L::c[i][a]) * fd[i];
+    }
+    const double ir = 1.0 / rho;
+    double u[3] = {0.0, 0.0, 0.0}, uu = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        u[a] = j[a] * ir;
+        uu += u[a] * u[a];
+    }
+    const double T = ((e + q.e_ref) * ir - 0.5 * uu) * q.inv_Cv;
+    double feq[Q];
+    feq_dev<L, double>(rho, u, T, feq);
+    const double s = taubar_of(q.mu_f, rho) / (2.0 * taubar_of(q.mu_c, rho));
+    const long long nf = x[0] + (long long)g.nf[0] * (x[1] + (long long)g.nf[1] * x[2]);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) F.f[(long long)i * g.Nf + nf] = S(feq[i] + s * (fd[i] - feq[i]));
+    F.e[nf] = S(e);
+#pragma unroll
+    for (int c = 0; c < D - 1; ++c) F.h2[(long long)c * g.Nf + nf] = S(0.5 * h[c]);
+}
+
+// Coarse node of restriction item k takes the values of its fine node, rescaled to the coarse level.
+template <class L, class S>
+__global__ void __launch_bounds__(RTPB) k_refine_restrict(RefineGeom g, RefineGas q, StateP<S> F, StateP<S> C) {
+    constexpr int D = L::D, Q = L::Q;
+    const long long k = (long long)blockIdx.x * RTPB + threadIdx.x;
+    if (k >= g.nrest) return;
+    int xf[3] = {0, 0, 0};
+    xf[0] = g.rlo[0] + 2 * (int)(k % g.rn[0]);
+    const long long r = k / g.rn[0];
+    xf[1] = g.rlo[1] + 2 * (int)(r % g.rn[1]);
+    if (D == 3) xf[2] = g.rlo[2] + 2 * (int)(r / g.rn[1]);
+    const long long nf = xf[0] + (long long)g.nf[0] * (xf[1] + (long long)g.nf[1] * xf[2]);
+    const long long nc = (g.org[0] + (xf[0] >> 1)) +
+                         (long long)g.nc[0] * ((g.org[1] + (xf[1] >> 1)) +
+                                               (long long)g.nc[1] * (D == 3 ? g.org[2] + (xf[2] >> 1) : 0));
+    double fd[Q], rho = 1.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        fd[i] = double(F.f[(long long)i * g.Nf + nf]);
+        rho += fd[i];
+#pragma unroll
+        for (int a = 0; a < D; ++a) j[a] += double(L::c[i][a]) * fd[i];
+    }
+    const double e = double(F.e[nf]);
+    const double ir = 1.0 / rho;
+    double u[3] = {0.0, 0.0, 0.0}, uu = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        u[a] = j[a] * ir;
+        uu += u[a] * u[a];
+    }
+    const double T = ((e + q.e_ref) * ir - 0.5 * uu) * q.inv_Cv;
+    double feq[Q];
+    feq_dev<L, double>(rho, u, T, feq);
+    const double s = 2.0 * taubar_of(q.mu_c, rho) / taubar_of(q.mu_f, rho);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) C.f[(long long)i * g.Nc + nc] = S(feq[i] + s * (fd[i] - feq[i]));
+    C.e[nc] = S(e);
+#pragma unroll
+    for (int c = 0; c < D - 1; ++c) C.h2[(long long)c * g.Nc + nc] = S(2.0 * double(F.h2[(long long)c * g.Nf + nf]));
+}
+
+unsigned blocks_of(long long n) { return (unsigned)((n + RTPB - 1) / RTPB); }
+
+template <class S>
+StateP<S> cur_of(lbm_handle* h) {
+    return h->cur == 0 ? stateA<S>(h) : stateB<S>(h);
+}
+template <class S>
+StateP<S> prev_of(lbm_handle* h) {
+    return h->cur == 0 ? stateB<S>(h) : stateA<S>(h);
+}
+
+template <class F>
+hipError_t dispatch2(lbm_handle* h, F&& f) {
+    if (h->D == 2) {
+        if (h->p.precision == LBM_F64) return f(D2Q9{}, double{});
+        return f(D2Q9{}, float{});
+    }
+    if (h->p.precision == LBM_F64) return f(D3Q19{}, double{});
+    return f(D3Q19{}, float{});
+}
+
+thread_local std::string g_refine_error;
+
+}  // namespace
+}  // namespace lbmib
+
+using namespace lbmib;
+
+struct lbm_refine {
+    lbm_handle* coarse = nullptr;
+    lbm_handle* fine = nullptr;
+    RefineGeom g{};
+    RefineGas q{};
+    int margin = 0;
+    std::string err;
+};
+
+namespace {
+
+int rfail(lbm_refine* r, int code, const std::string& msg) {
+    if (r)
+        r->err = msg;
+    else
+        g_refine_error = msg;
+    return code;
+}
+
+bool close_rel(double a, double b) { return std::fabs(a - b) <= 1e-12 * std::fabs(b); }
+
+// Body requirements, which ib_set_markers may change between steps.
+int check_bodies(lbm_refine* r) {
+    const lbm_handle* c = r->coarse;
+    const lbm_handle* f = r->fine;
+    if (c->markers_set) return rfail(r, LBM_E_INVAL, "the coarse handle holds a body");
+    if (f->markers_set) {
+        const int* fb = f->fbox;
+        const int D = f->D, M = r->margin;
+        // fbox: x, y, marching axis (y in 2D, z in 3D)
+        const int lo[3] = {fb[0], D == 3 ? fb[2] : fb[4], fb[4]};
+        const int hi[3] = {fb[1], D == 3 ? fb[3] : fb[5], fb[5]};
+        for (int a = 0; a < D; ++a)
+            if (lo[a] < M || hi[a] > r->g.nf[a] - 1 - M)
+                return rfail(r, LBM_E_INVAL, "fine body forced nodes closer than margin to the block edge");
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_refine_create(lbm_handle* coarse, lbm_handle* fine, const int* origin, int band, int margin,
+                      lbm_refine** out) {
+    if (!out) return rfail(nullptr, LBM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!coarse || !fine || !origin || coarse == fine) return rfail(nullptr, LBM_E_INVAL, "bad handles or origin");
+    const lbm_params &pc = coarse->p, &pf = fine->p;
+    const int D = pc.dim;
+    if (pf.dim != D) return rfail(nullptr, LBM_E_INVAL, "handles of different dimensions");
+    if (pf.precision != pc.precision) return rfail(nullptr, LBM_E_INVAL, "handles of different precisions");
+    if (coarse->device != fine->device || coarse->stream != fine->stream)
+        return rfail(nullptr, LBM_E_INVAL, "handles on different devices or streams");
+    bool same = pf.gamma == pc.gamma && pf.sigma == pc.sigma && pf.rho_inf == pc.rho_inf && pf.T_inf == pc.T_inf &&
+                pf.with_aC == pc.with_aC;
+    for (int a = 0; a < 3; ++a) same = same && pf.u_inf[a] == pc.u_inf[a];
+    if (!same) return rfail(nullptr, LBM_E_INVAL, "gas or free-stream parameters differ between the levels");
+    if (!close_rel(pf.mu, 2.0 * pc.mu) || !close_rel(pf.lambda_, 2.0 * pc.lambda_))
+        return rfail(nullptr, LBM_E_INVAL, "fine mu and lambda_ must be twice the coarse ones");
+    if (pf.bc_x != LBM_BC_PERIODIC) return rfail(nullptr, LBM_E_INVAL, "the fine handle must be periodic");
+    if (band < 2 || margin < band) return rfail(nullptr, LBM_E_INVAL, "need 2 <= band <= margin");
+    const int nc[3] = {pc.nx, pc.ny, pc.nz}, nf[3] = {pf.nx, pf.ny, pf.nz};
+    RefineGeom g{};
+    g.G = band;
+    for (int a = 0; a < 3; ++a) {
+        g.nc[a] = nc[a];
+        g.nf[a] = nf[a];
+        g.org[a] = a < D ? origin[a] : 0;
+        g.rlo[a] = 0;
+        g.rn[a] = 1;
+    }
+    g.Nc = coarse->N;
+    g.Nf = fine->N;
+    long long inner = 1;
+    g.nrest = 1;
+    for (int a = 0; a < D; ++a) {
+        if (nf[a] % 2 != 0 || nf[a] <= 2 * band)
+            return rfail(nullptr, LBM_E_INVAL, "fine node counts must be even and exceed twice the band");
+        if (g.org[a] < 0 || g.org[a] + nf[a] / 2 > nc[a] - 1)
+            return rfail(nullptr, LBM_E_INVAL, "block outside the coarse grid");
+        inner *= nf[a] - 2 * band;
+        // even fine indices in [margin, nf - 1 - margin]
+        const int lo = (margin + 1) & ~1, hi = nf[a] - 1 - margin;
+        g.rlo[a] = lo;
+        g.rn[a] = hi >= lo ? (hi - lo) / 2 + 1 : 0;
+        g.nrest *= g.rn[a];
+    }
+    if (pc.bc_x != LBM_BC_PERIODIC && (g.org[0] < 2 || g.org[0] + nf[0] / 2 > nc[0] - 3))
+        return rfail(nullptr, LBM_E_INVAL, "block overlaps the inflow or outflow columns");
+    g.nband = g.Nf - inner;
+    RefineGas q{};
+    q.mu_c = pc.mu;
+    q.mu_f = pf.mu;
+    q.inv_Cv = (pc.gamma - 1.0) * 3.0;
+    q.e_ref = coarse->args.fs.e_ref;
+    if (fine->args.fs.e_ref != q.e_ref) return rfail(nullptr, LBM_E_INVAL, "energy references differ");
+    lbm_refine* r = new (std::nothrow) lbm_refine();
+    if (!r) return rfail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    r->coarse = coarse;
+    r->fine = fine;
+    r->g = g;
+    r->q = q;
+    r->margin = margin;
+    *out = r;
+    return LBM_OK;
+}
+
+int lbm_refine_prolong(lbm_refine* r) {
+    if (!r) return LBM_E_INVAL;
+    lbm_handle *c = r->coarse, *f = r->fine;
+    hipError_t e = dispatch2(c, [&](auto L, auto S) {
+        using LT = decltype(L);
+        using ST = decltype(S);
+        hipLaunchKernelGGL((k_refine_prolong<LT, ST, true>), dim3(blocks_of(r->g.Nf)), dim3(RTPB), 0, c->stream,
+                           r->g, r->q, cur_of<ST>(c), cur_of<ST>(c), 1.0, cur_of<ST>(f));
+        return hipGetLastError();
+    });
+    if (e == hipSuccess && !f->geom.rows.empty()) {
+        const size_t nb = f->geom.rows.size() * (f->D == 3 ? 3 : 1) * 8;
+        e = hipMemsetAsync(f->d.h2off, 0, nb, f->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(f->d.h2off2, 0, nb, f->stream);
+    }
+    if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine prolong: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_refine_step(lbm_refine* r, int n) {
+    if (!r) return LBM_E_INVAL;
+    if (n < 0) return rfail(r, LBM_E_INVAL, "n < 0");
+    if (int rc = check_bodies(r)) return rc;
+    lbm_handle *c = r->coarse, *f = r->fine;
+    for (int s = 0; s < n; ++s) {
+        if (int rc = step_handle(c, 1, false)) return rfail(r, rc, std::string("coarse step: ") + c->err);
+        for (int k = 1; k <= 2; ++k) {
+            if (int rc = step_handle(f, 1, false)) return rfail(r, rc, std::string("fine step: ") + f->err);
+            // coarse: the previous state is the one before this coupled step, the current one after it
+            hipError_t e = dispatch2(c, [&](auto L, auto S) {
+                using LT = decltype(L);
+                using ST = decltype(S);
+                if (r->g.nband > 0)
+                    hipLaunchKernelGGL((k_refine_prolong<LT, ST, false>), dim3(blocks_of(r->g.nband)), dim3(RTPB), 0,
+                                       c->stream, r->g, r->q, prev_of<ST>(c), cur_of<ST>(c), 0.5 * k, cur_of<ST>(f));
+                return hipGetLastError();
+            });
+            if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine band: ") + hipGetErrorString(e));
+        }
+        hipError_t e = dispatch2(c, [&](auto L, auto S) {
+            using LT = decltype(L);
+            using ST = decltype(S);
+            if (r->g.nrest > 0)
+                hipLaunchKernelGGL((k_refine_restrict<LT, ST>), dim3(blocks_of(r->g.nrest)), dim3(RTPB), 0, c->stream,
+                                   r->g, r->q, cur_of<ST>(f), cur_of<ST>(c));
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine restrict: ") + hipGetErrorString(e));
+        if (s == n - 1)
+            if (int rc = residual_handle(c)) return rfail(r, rc, std::string("coarse residual: ") + c->err);
+    }
+    return LBM_OK;
+}
+
+void lbm_refine_destroy(lbm_refine* r) { delete r; }
+
+const char* lbm_refine_last_error(lbm_refine* r) { return r ? r->err.c_str() : g_refine_error.c_str(); }
+
+}  // extern "C"

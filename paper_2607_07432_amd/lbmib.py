@@ -25,6 +25,7 @@ EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step',
            'ib_geometry', 'ib_marker_state', 'lbm_destroy', 'lbm_last_error', 'lbm_stream_copy',
            'lbm_batch_workspace_bytes', 'lbm_batch_create', 'lbm_batch_step', 'lbm_batch_step_timed',
            'lbm_batch_set_tile', 'lbm_batch_config', 'lbm_batch_residuals', 'lbm_batch_destroy', 'lbm_batch_last_error',
+           'lbm_refine_create', 'lbm_refine_prolong', 'lbm_refine_step', 'lbm_refine_destroy', 'lbm_refine_last_error',
            'lbm_learn_input', 'lbm_learn_target', 'lbm_learn_warm_start',
            'nn_unet_param_count', 'nn_unet_workspace_bytes', 'nn_unet_create', 'nn_unet_set_params',
            'nn_unet_get_params', 'nn_unet_get_grads', 'nn_unet_forward', 'nn_unet_backward', 'nn_unet_adam', 'nn_unet_clip_grad_norm',
@@ -101,6 +102,13 @@ def load_library(path=LIB_PATH):
     lib.lbm_batch_destroy.restype = None
     lib.lbm_batch_last_error.argtypes = [vp]
     lib.lbm_batch_last_error.restype = ctypes.c_char_p
+    lib.lbm_refine_create.argtypes = [vp, vp, ip, i, i, P(vp)]
+    lib.lbm_refine_prolong.argtypes = [vp]
+    lib.lbm_refine_step.argtypes = [vp, i]
+    lib.lbm_refine_destroy.argtypes = [vp]
+    lib.lbm_refine_destroy.restype = None
+    lib.lbm_refine_last_error.argtypes = [vp]
+    lib.lbm_refine_last_error.restype = ctypes.c_char_p
     fp = P(ctypes.c_float)
     lib.lbm_learn_input.argtypes = [vp, d, d, d, vp]
     lib.lbm_learn_target.argtypes = [vp, vp]
@@ -402,6 +410,65 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Refinement:
+    """A fine Solver embedded in a coarse Solver (two-level grid, ratio 2; lbm_refine_* of the C ABI).
+
+    origin: coarse node of fine node 0 per axis (x, y[, z]). The fine solver must have been created
+    with twice the coarse mu and lambda_ and periodic closure (fine_params_for builds them)."""
+
+    def __init__(self, coarse, fine, origin, band=4, margin=8):
+        self.lib = load_library()
+        self.coarse, self.fine = coarse, fine
+        org = np.ascontiguousarray(list(origin) + [0] * (3 - len(origin)), dtype=np.int32)
+        r = ctypes.c_void_p()
+        rc = self.lib.lbm_refine_create(coarse.h, fine.h, _iptr(org), int(band), int(margin), ctypes.byref(r))
+        if rc != LBM_OK:
+            raise LbmError(rc, self.lib.lbm_refine_last_error(None).decode())
+        self.r = r
+
+    def _check(self, rc):
+        if rc != LBM_OK:
+            raise LbmError(rc, self.lib.lbm_refine_last_error(self.r).decode())
+        return rc
+
+    def prolong(self):
+        """Every fine node from the current coarse state."""
+        self._check(self.lib.lbm_refine_prolong(self.r))
+
+    def step(self, n=1):
+        self._check(self.lib.lbm_refine_step(self.r, int(n)))
+
+    def residual(self):
+        """Coarse residual of the last coupled step (restriction included)."""
+        return self.coarse.residual()
+
+    def close(self):
+        if getattr(self, 'r', None):
+            self.lib.lbm_refine_destroy(self.r)
+            self.r = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fine_params_for(coarse_params, fine_cells, max_markers=1):
+    """Parameters of the fine level of a block of fine_cells[a] coarse cells per axis: 2 fine_cells[a]
+    nodes, twice the coarse mu and lambda_, periodic closure, the coarse gas and free stream."""
+    p = Params()
+    ctypes.memmove(ctypes.byref(p), ctypes.byref(coarse_params), ctypes.sizeof(Params))
+    p.nx = 2 * fine_cells[0]
+    p.ny = 2 * fine_cells[1]
+    p.nz = 2 * fine_cells[2] if coarse_params.dim == 3 else 1
+    p.mu = 2.0 * coarse_params.mu
+    p.lambda_ = 2.0 * coarse_params.lambda_
+    p.bc_x = BC_PERIODIC
+    p.max_markers = max_markers
+    return p
 
 
 NN_OK = 0

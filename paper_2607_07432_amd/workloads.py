@@ -298,6 +298,64 @@ def precision_case(nx=512, ny=256, nz=256, center=None):
     return sphere_case(nx=nx, ny=ny, nz=nz, center=center, mach=0.2, reynolds=300.0, T_wall_ratio=1.2)
 
 
+def _refined_temperatures(mach, reynolds, fine_len, T_wall_ratio):
+    """(T_inf, T_w, thermal kind, value) with the temperature rule applied on the fine level, where
+    the body spans twice the coarse nodes and the conduction number is twice the coarse one."""
+    if T_wall_ratio is None:
+        T_inf = lattice_temperature(mach, reynolds, fine_len)
+        return T_inf, T_inf, T_NEUMANN, 0.0
+    T_inf, T_w = reference_temperatures(T_wall_ratio, mach, reynolds, fine_len)
+    return T_inf, T_w, T_DIRICHLET, T_w
+
+
+def refined_cylinder(nx=120, ny=64, origin=(24, 12), block=(40, 40), diameter=10.0, center=None, mach=0.2,
+                     reynolds=40.0, T_wall_ratio=None, bc='inflow_outflow', method=METHOD_FODIBM_R, steps=1):
+    """2D cylinder of `diameter` coarse cells inside a refined block: the coarse grid nx x ny
+    (no body; closure bc along x), and a block of block[a] coarse cells at coarse node `origin`
+    whose fine grid has twice the resolution and holds the body (2 diameter nodes across, about one
+    marker per fine node of perimeter). Re on the diameter; the free-stream temperature is chosen
+    for the fine level. Returns (coarse case, fine case, origin); the fine case has doubled mu and
+    lambda, periodic closure, and marker positions in fine lattice units."""
+    if center is None:
+        center = (origin[0] + 0.35 * block[0] + 0.23, origin[1] + 0.5 * block[1] + 0.17)
+    Df = 2.0 * diameter
+    T_inf, T_w, kind, tv = _refined_temperatures(mach, reynolds, Df, T_wall_ratio)
+    u, mu, lam = flow_units(mach, reynolds, diameter, T_inf)
+    coarse = Case(name='refined_cylinder_coarse', dim=2, dims=(nx, ny), mu=mu, lam=lam, u_inf=(u, 0.0),
+                  T_inf=T_inf, bc=bc, method=method, ref_len=diameter, ref_area=diameter,
+                  surface=math.pi * diameter, T_wall=T_w, steps=steps)
+    cf = (2.0 * (center[0] - origin[0]), 2.0 * (center[1] - origin[1]))
+    X, n = cylinder_markers(cf, Df / 2.0, int(round(math.pi * Df)))
+    fine = Case(name='refined_cylinder_fine', dim=2, dims=(2 * block[0], 2 * block[1]), mu=2.0 * mu,
+                lam=2.0 * lam, u_inf=(u, 0.0), T_inf=T_inf, bc='periodic', method=method, ref_len=Df,
+                ref_area=Df, surface=math.pi * Df, T_wall=T_w, steps=steps, **_markers_common(X, n, kind, tv))
+    return coarse, fine, tuple(origin)
+
+
+def refined_sphere(nx=48, ny=32, nz=32, origin=(10, 6, 6), block=(20, 20, 20), diameter=6.0, center=None,
+                   mach=0.2, reynolds=50.0, T_wall_ratio=None, bc='inflow_outflow', method=METHOD_FODIBM_R,
+                   markers=None, steps=1):
+    """3D analogue of refined_cylinder: a sphere of `diameter` coarse cells in a refined block
+    (markers: about pi (2 diameter)^2 unless given)."""
+    if center is None:
+        center = (origin[0] + 0.4 * block[0] + 0.23, origin[1] + 0.5 * block[1] + 0.17,
+                  origin[2] + 0.5 * block[2] - 0.11)
+    Df = 2.0 * diameter
+    T_inf, T_w, kind, tv = _refined_temperatures(mach, reynolds, Df, T_wall_ratio)
+    u, mu, lam = flow_units(mach, reynolds, diameter, T_inf)
+    coarse = Case(name='refined_sphere_coarse', dim=3, dims=(nx, ny, nz), mu=mu, lam=lam, u_inf=(u, 0.0, 0.0),
+                  T_inf=T_inf, bc=bc, method=method, ref_len=diameter, ref_area=math.pi * diameter ** 2 / 4,
+                  surface=math.pi * diameter ** 2, T_wall=T_w, steps=steps)
+    cf = tuple(2.0 * (center[a] - origin[a]) for a in range(3))
+    m = markers if markers is not None else int(round(math.pi * Df * Df))
+    X, n = sphere_markers(cf, Df / 2.0, m)
+    fine = Case(name='refined_sphere_fine', dim=3, dims=tuple(2 * b for b in block), mu=2.0 * mu, lam=2.0 * lam,
+                u_inf=(u, 0.0, 0.0), T_inf=T_inf, bc='periodic', method=method, ref_len=Df,
+                ref_area=math.pi * Df ** 2 / 4, surface=math.pi * Df ** 2, T_wall=T_w, steps=steps,
+                **_markers_common(X, n, kind, tv))
+    return coarse, fine, tuple(origin)
+
+
 def acoustic_pulse(nx=160, ny=4, u_inf=0.1, amp=1e-3, x0=60.0, width=6.0, mu=0.005, bc='characteristic',
                    sigma_c=0.0):
     """A plane right-running isentropic pressure pulse on a stream along x (2D, no body, periodic
