@@ -2,8 +2,10 @@
 // refilled from the coarse grid and by restriction of the fine block (contract in include/lbmib.h).
 //
 // Both transfers are gathers with one thread per destination node, FP64 arithmetic whatever the
-// storage precision. A band node reads 2^D coarse nodes of two states (time interpolation); a
-// restricted coarse node reads one fine node. Their traffic is a few per cent of the fine sweeps'.
+// storage precision. A band node combines the y (and z) corners of its coarse column, from two
+// coarse states after the first fine step (time interpolation) and from one after the second; an
+// odd-x node takes the neighbouring column from the next lane. A restricted coarse node reads one
+// fine node.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -70,24 +72,65 @@ __device__ __forceinline__ void band_node(const RefineGeom& g, long long k, int*
     x[0] = c < G ? c : nx - 2 * G + c;
 }
 
-// Populations f~ (deviations), e and h2 interpolated at fine node x from the coarse states
-// (1 - wt) A + wt B (multilinear in space), then rescaled to the fine level and stored.
-template <class L, class S, bool ALL>
-__global__ void __launch_bounds__(RTPB) k_refine_prolong(RefineGeom g, RefineGas q, StateP<S> A, StateP<S> B,
-                                                         double wt, StateP<S> F) {
-    constexpr int D = L::D, Q = L::Q;
-    const long long k = (long long)blockIdx.x * RTPB + threadIdx.x;
-    int x[3] = {0, 0, 0};
+// Fine coordinates of item k: every fine node (ALL, x fastest) or the band nodes.
+template <int D, bool ALL>
+__device__ __forceinline__ void node_of(const RefineGeom& g, long long k, int* x) {
     if (ALL) {
-        if (k >= g.Nf) return;
         x[0] = (int)(k % g.nf[0]);
         const long long r = k / g.nf[0];
         x[1] = (int)(r % g.nf[1]);
         x[2] = (int)(r / g.nf[1]);
     } else {
-        if (k >= g.nband) return;
         band_node<D>(g, k, x);
     }
+}
+
+// Values of coarse column ix combined over the y (and z) corners of a fine node: for the Q
+// populations f~, e and the D - 1 stored history components, sum over corners of w_yz times the
+// state (1 - wt) A + wt B (B alone unless TWO).
+template <class L, class S, bool TWO>
+__device__ __forceinline__ void gather_yz(const RefineGeom& g, const StateP<S>& A, const StateP<S>& B, double wt,
+                                          int ix, const int* i0, const double* fr, double* Y) {
+    constexpr int D = L::D, Q = L::Q, NV = Q + D;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Y[v] = 0.0;
+    const double wa = 1.0 - wt;
+#pragma unroll
+    for (int cb = 0; cb < (1 << (D - 1)); ++cb) {
+        const int by = cb & 1, bz = (cb >> 1) & 1;
+        double w = by ? fr[1] : 1.0 - fr[1];
+        if (D == 3) w *= bz ? fr[2] : 1.0 - fr[2];
+        if (w == 0.0) continue;   // the same for every node of a row
+        const long long n = ix + (long long)g.nc[0] * ((i0[1] + by) + (long long)g.nc[1] * (i0[2] + bz));
+        auto at = [&](const S* a, const S* b, long long off) {
+            const double vb = double(b[off]);
+            return TWO ? wa * double(a[off]) + wt * vb : vb;
+        };
+#pragma unroll
+        for (int i = 0; i < Q; ++i) Y[i] += w * at(A.f, B.f, (long long)i * g.Nc + n);
+        Y[Q] += w * at(A.e, B.e, n);
+#pragma unroll
+        for (int c = 0; c < D - 1; ++c) Y[Q + 1 + c] += w * at(A.h2, B.h2, (long long)c * g.Nc + n);
+    }
+}
+
+// Populations f~ (deviations), e and h2 interpolated at a fine node from the coarse states
+// (1 - wt) A + wt B (multilinear in space), rescaled to the fine level and stored.
+// Separable: each lane combines the y/z corners of its own coarse column; an odd-x node takes the
+// next column from the next lane when that lane holds the next node of the row (a row's nodes are
+// consecutive items), else it gathers that column itself.
+template <class L, class S, bool ALL, bool TWO>
+__global__ void __launch_bounds__(RTPB) k_refine_prolong(RefineGeom g, RefineGas q, StateP<S> A, StateP<S> B,
+                                                         double wt, StateP<S> F) {
+    constexpr int D = L::D, Q = L::Q, NV = Q + D;
+    const long long total = ALL ? g.Nf : g.nband;
+    const long long kk = (long long)blockIdx.x * RTPB + threadIdx.x;
+    const bool active = kk < total;
+    const long long k = active ? kk : total - 1;   // idle lanes still take part in the shuffle
+    int x[3] = {0, 0, 0}, xn[3] = {0, 0, 0};
+    node_of<D, ALL>(g, k, x);
+    node_of<D, ALL>(g, k + 1 < total ? k + 1 : k, xn);
+    const bool next_ok = (threadIdx.x & 63) != 63 && xn[0] == x[0] + 1 && xn[1] == x[1] && xn[2] == x[2];
     int i0[3];
     double fr[3];
 #pragma unroll
@@ -95,39 +138,22 @@ __global__ void __launch_bounds__(RTPB) k_refine_prolong(RefineGeom g, RefineGas
         i0[a] = a < D ? g.org[a] + (x[a] >> 1) : 0;
         fr[a] = a < D ? 0.5 * (x[a] & 1) : 0.0;
     }
-    double fd[Q], e = 0.0, h[D - 1];
+    double Y[NV], Yn[NV];
+    gather_yz<L, S, TWO>(g, A, B, wt, i0[0], i0, fr, Y);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) fd[i] = 0.0;
+    for (int v = 0; v < NV; ++v) Yn[v] = __shfl_down(Y[v], 1, 64);
+    if (x[0] & 1) {
+        if (!next_ok) gather_yz<L, S, TWO>(g, A, B, wt, i0[0] + 1, i0, fr, Yn);
 #pragma unroll
-    for (int c = 0; c < D - 1; ++c) h[c] = 0.0;
-    const double wa = 1.0 - wt;
-    // corners in the order (x bit, y bit[, z bit]) with the x bit slowest
-#pragma unroll
-    for (int cb = 0; cb < (1 << D); ++cb) {
-        double w = 1.0;
-        int ci[3] = {0, 0, 0};
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const int bit = (cb >> (D - 1 - a)) & 1;
-            w *= bit ? fr[a] : 1.0 - fr[a];
-            ci[a] = i0[a] + bit;
-        }
-        if (w == 0.0) continue;
-        const long long n = ci[0] + (long long)g.nc[0] * (ci[1] + (long long)g.nc[1] * ci[2]);
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            fd[i] += w * (wa * double(A.f[(long long)i * g.Nc + n]) + wt * double(B.f[(long long)i * g.Nc + n]));
-        e += w * (wa * double(A.e[n]) + wt * double(B.e[n]));
-#pragma unroll
-        for (int c = 0; c < D - 1; ++c)
-            h[c] += w * (wa * double(A.h2[(long long)c * g.Nc + n]) + wt * double(B.h2[(long long)c * g.Nc + n]));
+        for (int v = 0; v < NV; ++v) Y[v] = 0.5 * Y[v] + 0.5 * Yn[v];
     }
+    if (!active) return;
     double rho = 1.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        rho += fd[i];
+        rho += Y[i];
 #pragma unroll
-        for (int a = 0; a < D; ++a) j[a] += double(L::c[i][a]) * fd[i];
+        for (int a = 0; a < D; ++a) j[a] += double(L::c[i][a]) * Y[i];
     }
     const double ir = 1.0 / rho;
     double u[3] = {0.0, 0.0, 0.0}, uu = 0.0;
@@ -136,16 +162,17 @@ __global__ void __launch_bounds__(RTPB) k_refine_prolong(RefineGeom g, RefineGas
         u[a] = j[a] * ir;
         uu += u[a] * u[a];
     }
+    const double e = Y[Q];
     const double T = ((e + q.e_ref) * ir - 0.5 * uu) * q.inv_Cv;
     double feq[Q];
     feq_dev<L, double>(rho, u, T, feq);
     const double s = taubar_of(q.mu_f, rho) / (2.0 * taubar_of(q.mu_c, rho));
     const long long nf = x[0] + (long long)g.nf[0] * (x[1] + (long long)g.nf[1] * x[2]);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) F.f[(long long)i * g.Nf + nf] = S(feq[i] + s * (fd[i] - feq[i]));
+    for (int i = 0; i < Q; ++i) F.f[(long long)i * g.Nf + nf] = S(feq[i] + s * (Y[i] - feq[i]));
     F.e[nf] = S(e);
 #pragma unroll
-    for (int c = 0; c < D - 1; ++c) F.h2[(long long)c * g.Nf + nf] = S(0.5 * h[c]);
+    for (int c = 0; c < D - 1; ++c) F.h2[(long long)c * g.Nf + nf] = S(0.5 * Y[Q + 1 + c]);
 }
 
 // Coarse node of restriction item k takes the values of its fine node, rescaled to the coarse level.
@@ -332,8 +359,8 @@ int lbm_refine_prolong(lbm_refine* r) {
     hipError_t e = dispatch2(c, [&](auto L, auto S) {
         using LT = decltype(L);
         using ST = decltype(S);
-        hipLaunchKernelGGL((k_refine_prolong<LT, ST, true>), dim3(blocks_of(r->g.Nf)), dim3(RTPB), 0, c->stream,
-                           r->g, r->q, cur_of<ST>(c), cur_of<ST>(c), 1.0, cur_of<ST>(f));
+        hipLaunchKernelGGL((k_refine_prolong<LT, ST, true, false>), dim3(blocks_of(r->g.Nf)), dim3(RTPB), 0,
+                           c->stream, r->g, r->q, cur_of<ST>(c), cur_of<ST>(c), 1.0, cur_of<ST>(f));
         return hipGetLastError();
     });
     if (e == hipSuccess && !f->geom.rows.empty()) {
@@ -358,9 +385,14 @@ int lbm_refine_step(lbm_refine* r, int n) {
             hipError_t e = dispatch2(c, [&](auto L, auto S) {
                 using LT = decltype(L);
                 using ST = decltype(S);
-                if (r->g.nband > 0)
-                    hipLaunchKernelGGL((k_refine_prolong<LT, ST, false>), dim3(blocks_of(r->g.nband)), dim3(RTPB), 0,
-                                       c->stream, r->g, r->q, prev_of<ST>(c), cur_of<ST>(c), 0.5 * k, cur_of<ST>(f));
+                // at k = 2 the band takes the coarse state after the step alone
+                if (r->g.nband > 0 && k == 1)
+                    hipLaunchKernelGGL((k_refine_prolong<LT, ST, false, true>), dim3(blocks_of(r->g.nband)), dim3(RTPB),
+                                       0, c->stream, r->g, r->q, prev_of<ST>(c), cur_of<ST>(c), 0.5, cur_of<ST>(f));
+                else if (r->g.nband > 0)
+                    hipLaunchKernelGGL((k_refine_prolong<LT, ST, false, false>), dim3(blocks_of(r->g.nband)),
+                                       dim3(RTPB), 0, c->stream, r->g, r->q, prev_of<ST>(c), cur_of<ST>(c), 1.0,
+                                       cur_of<ST>(f));
                 return hipGetLastError();
             });
             if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine band: ") + hipGetErrorString(e));
