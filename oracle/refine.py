@@ -1,4 +1,4 @@
-"""Two-level static grid refinement (ratio 2): a fine block embedded in the coarse grid, 2D or 3D.
+"""Static grid refinement (ratio 2): fine blocks embedded in a coarse grid, 2D or 3D, nested to any depth.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -20,7 +20,9 @@ methods in general):
     is not transferred (each level keeps what its own step produced);
   * after the fine steps, the coarse nodes whose fine counterpart lies at least R fine nodes inside
     the block on every axis take the fine values (restriction); the coarse grid is stepped
-    everywhere.
+    everywhere;
+  * levels nest: a block may itself hold a finer block, coupled to it in the same way, so that
+    level k takes 2^k steps per step of level 0; a body lies on the finest level.
 The coupling is not conservative (interpolation, not flux matching).
 """
 import itertools
@@ -169,18 +171,46 @@ def restrict(lat, prm_c, prm_f, st_c, st_f, block):
     return st_c
 
 
+def nested_step(lat, prm_0, states, blocks, finest_forcing=None):
+    """One step of level 0 of nested blocks: level k + 1 lies in level k at blocks[k] and takes two
+    steps per step of level k, each followed by its band refill from level k, and restricts onto
+    level k at the end of level k's step (so level k takes 2^k steps per step of level 0). A body,
+    if any, is on the finest level: finest_forcing(state) -> (fib, fE). Returns the new states,
+    coarsest first."""
+    states = list(states)
+
+    def advance(k, prm):
+        if k == len(states) - 1:
+            fib, fE = finest_forcing(states[k]) if finest_forcing else (None, None)
+            states[k] = L.lbm_step(lat, prm, states[k], fib, fE)
+            return
+        old = states[k]
+        new = L.lbm_step(lat, prm, old)
+        states[k] = new
+        prm_f = fine_params(prm)
+        for s in (1, 2):
+            advance(k + 1, prm_f)
+            states[k + 1] = fill_band(lat, prm, prm_f, states[k + 1], old, new, 0.5 * s, blocks[k])
+        states[k] = restrict(lat, prm, prm_f, states[k], states[k + 1], blocks[k])
+
+    advance(0, prm_0)
+    return states
+
+
 def refined_step(lat, prm_c, st_c, st_f, block, fine_forcing=None):
     """One coarse step of the two-level grid. fine_forcing(st_f) -> (fib, fE) of the fine body
     (None: no body). Returns the new coarse and fine states."""
-    prm_f = fine_params(prm_c)
-    new_c = L.lbm_step(lat, prm_c, st_c)
-    st = st_f
-    for k in (1, 2):
-        fib, fE = fine_forcing(st) if fine_forcing else (None, None)
-        st = L.lbm_step(lat, prm_f, st, fib, fE)
-        st = fill_band(lat, prm_c, prm_f, st, st_c, new_c, 0.5 * k, block)
-    new_c = restrict(lat, prm_c, prm_f, new_c, st, block)
-    return new_c, st
+    new_c, new_f = nested_step(lat, prm_c, [st_c, st_f], [block], fine_forcing)
+    return new_c, new_f
+
+
+def initial_nest(lat, prm_0, st_0, blocks):
+    """States of every level of a nest, each finer one prolonged from the one containing it."""
+    states, prm = [st_0], prm_0
+    for blk in blocks:
+        states.append(initial_fine(lat, prm, states[-1], blk))
+        prm = fine_params(prm)
+    return states
 
 
 def initial_fine(lat, prm_c, st_c, block):

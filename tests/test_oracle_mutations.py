@@ -149,8 +149,8 @@ MUTATIONS = [
      'non-equilibrium populations not rescaled from coarse to fine'),
     ('refine.py', 'mu=2.0 * prm_c.mu, lam=2.0 * prm_c.lam', 'mu=prm_c.mu, lam=prm_c.lam',
      T + 'test_oracle_refine.py::test_shear_wave_crosses_the_block', 'fine viscosity not doubled in lattice units'),
-    ('refine.py', 'fill_band(lat, prm_c, prm_f, st, st_c, new_c, 0.5 * k, block)',
-     'fill_band(lat, prm_c, prm_f, st, st_c, new_c, 1.0, block)',
+    ('refine.py', 'fill_band(lat, prm, prm_f, states[k + 1], old, new, 0.5 * s, blocks[k])',
+     'fill_band(lat, prm, prm_f, states[k + 1], old, new, 1.0, blocks[k])',
      T + 'test_oracle_refine.py::test_acoustic_pulse_crosses_the_block', 'no time interpolation of the band'),
     ('refine.py', 'frac.append((xf % 2) * 0.5)', 'frac.append((xf % 2) * 0.0)',
      T + 'test_oracle_refine.py::test_acoustic_pulse_crosses_the_block', 'no spatial interpolation of the band'),
@@ -166,6 +166,15 @@ MUTATIONS = [
      T + 'test_oracle_refine.py::test_band_and_restriction_sets', 'band one node short at the upper edges'),
     ('refine.py', 'i = i[(i >= block.R) & (i <= n - 1 - block.R)]', 'i = i[(i > block.R) & (i <= n - 1 - block.R)]',
      T + 'test_oracle_refine.py::test_band_and_restriction_sets', 'restriction margin off by one'),
+    ('refine.py', 'advance(k + 1, prm_f)', 'advance(k + 1, prm_f if k == 0 else prm)',
+     T + 'test_oracle_refine.py::test_shear_wave_error_falls_with_each_level', 'third level viscosity doubled once only'),
+    ('refine.py', 'states[k] = restrict(lat, prm, prm_f, states[k], states[k + 1], blocks[k])',
+     'states[k] = restrict(lat, prm, prm_f, states[k], states[k + 1], blocks[k]) if k == 0 else states[k]',
+     T + 'test_oracle_refine.py::test_shear_wave_error_falls_with_each_level', 'inner level not restricted'),
+    ('refine.py', 'states[k + 1] = fill_band(lat, prm, prm_f, states[k + 1], old, new, 0.5 * s, blocks[k])',
+     'states[k + 1] = fill_band(lat, prm, prm_f, states[k + 1], old, new, 0.5 * s if k == 0 else 1.0, blocks[k])',
+     T + 'test_oracle_refine.py::test_acoustic_pulse_crosses_a_nest_of_three_levels',
+     'inner band taken from the end of the middle step'),
 ]
 
 
