@@ -284,12 +284,24 @@ int lbm_refine_create(lbm_handle* coarse, lbm_handle* fine, const int* origin, i
  * Errors: LBM_E_INVAL, LBM_E_HIP. */
 int lbm_refine_prolong(lbm_refine* r);
 
-/* Enqueue n coupled steps. The last one leaves in the coarse handle the residual (lbm_residual)
- * between the coarse states before and after it, restriction included. Asynchronous.
- * Errors: LBM_E_INVAL (n < 0, a body requirement broken), LBM_E_HIP. */
+/* Enqueue n coupled steps (with every nested level, see lbm_refine_nest). The last one leaves in
+ * the coarse handle the residual (lbm_residual) between the coarse states before and after it,
+ * restriction included. Asynchronous.
+ * Errors: LBM_E_INVAL (n < 0, a body requirement broken, a nested coupling), LBM_E_HIP. */
 int lbm_refine_step(lbm_refine* r, int n);
 
-/* Release the coupling (not the handles). */
+/* Nest two couplings: inner couples a finer block to outer's fine handle (inner's coarse handle
+ * must be outer's fine handle). Stepping outer then advances the fine level through inner: each
+ * of its two steps is one coupled step of inner (so level k of a nest takes 2^k steps per step of
+ * the outermost coarse level), and inner itself may hold a further nesting. The body, if any, is
+ * on the finest handle; the middle handles hold none. Only the outermost coupling is stepped
+ * (lbm_refine_step on a nested coupling returns LBM_E_INVAL). Requirement: the inner block lies at
+ * least `band` nodes of the middle level inside that level's edges (its band holds wrapped values
+ * until the outer coupling refills it). Errors: LBM_E_INVAL (handles do not match, already nested,
+ * a cycle, the placement). */
+int lbm_refine_nest(lbm_refine* outer, lbm_refine* inner);
+
+/* Release the coupling (not the handles); a nesting it takes part in is undone. */
 void lbm_refine_destroy(lbm_refine* r);
 
 /* Message of the last error of this coupling (of the last failed lbm_refine_create if r is NULL). */

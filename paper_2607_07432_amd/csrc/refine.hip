@@ -251,6 +251,8 @@ struct lbm_refine {
     RefineGeom g{};
     RefineGas q{};
     int margin = 0;
+    lbm_refine* child = nullptr;    // coupling of the fine handle with a finer block, or NULL
+    lbm_refine* parent = nullptr;   // coupling whose fine handle is this one's coarse handle
     std::string err;
 };
 
@@ -266,8 +268,8 @@ int rfail(lbm_refine* r, int code, const std::string& msg) {
 
 bool close_rel(double a, double b) { return std::fabs(a - b) <= 1e-12 * std::fabs(b); }
 
-// Body requirements, which ib_set_markers may change between steps.
-int check_bodies(lbm_refine* r) {
+// Body requirements of one coupling, which ib_set_markers may change between steps.
+int check_bodies_one(lbm_refine* r) {
     const lbm_handle* c = r->coarse;
     const lbm_handle* f = r->fine;
     if (c->markers_set) return rfail(r, LBM_E_INVAL, "the coarse handle holds a body");
@@ -281,6 +283,54 @@ int check_bodies(lbm_refine* r) {
             if (lo[a] < M || hi[a] > r->g.nf[a] - 1 - M)
                 return rfail(r, LBM_E_INVAL, "fine body forced nodes closer than margin to the block edge");
     }
+    return LBM_OK;
+}
+
+// The same for a coupling and every coupling nested inside it.
+int check_bodies(lbm_refine* r) {
+    if (r->child) {
+        if (int rc = check_bodies_one(r)) return rc;
+        if (int rc = check_bodies(r->child)) return rfail(r, rc, "inner level: " + r->child->err);
+        return LBM_OK;
+    }
+    return check_bodies_one(r);
+}
+
+// One coupled step of r: the coarse step, then two steps of the fine level (each a coupled step
+// of the nested coupling if there is one) each followed by its band refill, then the restriction.
+int coupled_step(lbm_refine* r) {
+    lbm_handle *c = r->coarse, *f = r->fine;
+    if (int rc = step_handle(c, 1, false)) return rfail(r, rc, std::string("coarse step: ") + c->err);
+    for (int k = 1; k <= 2; ++k) {
+        if (r->child) {
+            if (int rc = coupled_step(r->child)) return rfail(r, rc, "inner level: " + r->child->err);
+        } else if (int rc = step_handle(f, 1, false)) {
+            return rfail(r, rc, std::string("fine step: ") + f->err);
+        }
+        // coarse: the previous state is the one before this coupled step, the current one after it
+        hipError_t e = dispatch2(c, [&](auto L, auto S) {
+            using LT = decltype(L);
+            using ST = decltype(S);
+            // at k = 2 the band takes the coarse state after the step alone
+            if (r->g.nband > 0 && k == 1)
+                hipLaunchKernelGGL((k_refine_prolong<LT, ST, false, true>), dim3(blocks_of(r->g.nband)), dim3(RTPB), 0,
+                                   c->stream, r->g, r->q, prev_of<ST>(c), cur_of<ST>(c), 0.5, cur_of<ST>(f));
+            else if (r->g.nband > 0)
+                hipLaunchKernelGGL((k_refine_prolong<LT, ST, false, false>), dim3(blocks_of(r->g.nband)), dim3(RTPB),
+                                   0, c->stream, r->g, r->q, prev_of<ST>(c), cur_of<ST>(c), 1.0, cur_of<ST>(f));
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine band: ") + hipGetErrorString(e));
+    }
+    hipError_t e = dispatch2(c, [&](auto L, auto S) {
+        using LT = decltype(L);
+        using ST = decltype(S);
+        if (r->g.nrest > 0)
+            hipLaunchKernelGGL((k_refine_restrict<LT, ST>), dim3(blocks_of(r->g.nrest)), dim3(RTPB), 0, c->stream,
+                               r->g, r->q, cur_of<ST>(f), cur_of<ST>(c));
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine restrict: ") + hipGetErrorString(e));
     return LBM_OK;
 }
 
@@ -375,44 +425,42 @@ int lbm_refine_prolong(lbm_refine* r) {
 int lbm_refine_step(lbm_refine* r, int n) {
     if (!r) return LBM_E_INVAL;
     if (n < 0) return rfail(r, LBM_E_INVAL, "n < 0");
+    if (r->parent) return rfail(r, LBM_E_INVAL, "a nested coupling is stepped through its outer coupling");
     if (int rc = check_bodies(r)) return rc;
-    lbm_handle *c = r->coarse, *f = r->fine;
     for (int s = 0; s < n; ++s) {
-        if (int rc = step_handle(c, 1, false)) return rfail(r, rc, std::string("coarse step: ") + c->err);
-        for (int k = 1; k <= 2; ++k) {
-            if (int rc = step_handle(f, 1, false)) return rfail(r, rc, std::string("fine step: ") + f->err);
-            // coarse: the previous state is the one before this coupled step, the current one after it
-            hipError_t e = dispatch2(c, [&](auto L, auto S) {
-                using LT = decltype(L);
-                using ST = decltype(S);
-                // at k = 2 the band takes the coarse state after the step alone
-                if (r->g.nband > 0 && k == 1)
-                    hipLaunchKernelGGL((k_refine_prolong<LT, ST, false, true>), dim3(blocks_of(r->g.nband)), dim3(RTPB),
-                                       0, c->stream, r->g, r->q, prev_of<ST>(c), cur_of<ST>(c), 0.5, cur_of<ST>(f));
-                else if (r->g.nband > 0)
-                    hipLaunchKernelGGL((k_refine_prolong<LT, ST, false, false>), dim3(blocks_of(r->g.nband)),
-                                       dim3(RTPB), 0, c->stream, r->g, r->q, prev_of<ST>(c), cur_of<ST>(c), 1.0,
-                                       cur_of<ST>(f));
-                return hipGetLastError();
-            });
-            if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine band: ") + hipGetErrorString(e));
-        }
-        hipError_t e = dispatch2(c, [&](auto L, auto S) {
-            using LT = decltype(L);
-            using ST = decltype(S);
-            if (r->g.nrest > 0)
-                hipLaunchKernelGGL((k_refine_restrict<LT, ST>), dim3(blocks_of(r->g.nrest)), dim3(RTPB), 0, c->stream,
-                                   r->g, r->q, cur_of<ST>(f), cur_of<ST>(c));
-            return hipGetLastError();
-        });
-        if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine restrict: ") + hipGetErrorString(e));
+        if (int rc = coupled_step(r)) return rc;
         if (s == n - 1)
-            if (int rc = residual_handle(c)) return rfail(r, rc, std::string("coarse residual: ") + c->err);
+            if (int rc = residual_handle(r->coarse))
+                return rfail(r, rc, std::string("coarse residual: ") + r->coarse->err);
     }
     return LBM_OK;
 }
 
-void lbm_refine_destroy(lbm_refine* r) { delete r; }
+int lbm_refine_nest(lbm_refine* outer, lbm_refine* inner) {
+    if (!outer || !inner || outer == inner) return LBM_E_INVAL;
+    if (inner->coarse != outer->fine)
+        return rfail(outer, LBM_E_INVAL, "the inner coupling's coarse handle is not the outer one's fine handle");
+    if (outer->child || inner->parent) return rfail(outer, LBM_E_INVAL, "already nested");
+    for (const lbm_refine* p = outer; p; p = p->parent)
+        if (p == inner) return rfail(outer, LBM_E_INVAL, "nesting would form a cycle");
+    // the inner block and the coarse nodes its band reads stay clear of the middle level's band,
+    // which holds wrapped values until the outer coupling refills it
+    const RefineGeom &go = outer->g, &gi = inner->g;
+    const int D = outer->fine->D;
+    for (int a = 0; a < D; ++a)
+        if (gi.org[a] < go.G || gi.org[a] + gi.nf[a] / 2 > go.nf[a] - 1 - go.G)
+            return rfail(outer, LBM_E_INVAL, "inner block within the band of the middle level");
+    outer->child = inner;
+    inner->parent = outer;
+    return LBM_OK;
+}
+
+void lbm_refine_destroy(lbm_refine* r) {
+    if (!r) return;
+    if (r->parent) r->parent->child = nullptr;
+    if (r->child) r->child->parent = nullptr;
+    delete r;
+}
 
 const char* lbm_refine_last_error(lbm_refine* r) { return r ? r->err.c_str() : g_refine_error.c_str(); }
 

@@ -25,7 +25,8 @@ EXPORTS = ['lbm_workspace_bytes', 'lbm_init_grid', 'ib_set_markers', 'lbm_step',
            'ib_geometry', 'ib_marker_state', 'lbm_destroy', 'lbm_last_error', 'lbm_stream_copy',
            'lbm_batch_workspace_bytes', 'lbm_batch_create', 'lbm_batch_step', 'lbm_batch_step_timed',
            'lbm_batch_set_tile', 'lbm_batch_config', 'lbm_batch_residuals', 'lbm_batch_destroy', 'lbm_batch_last_error',
-           'lbm_refine_create', 'lbm_refine_prolong', 'lbm_refine_step', 'lbm_refine_destroy', 'lbm_refine_last_error',
+           'lbm_refine_create', 'lbm_refine_prolong', 'lbm_refine_step', 'lbm_refine_nest', 'lbm_refine_destroy',
+           'lbm_refine_last_error',
            'lbm_learn_input', 'lbm_learn_target', 'lbm_learn_warm_start',
            'nn_unet_param_count', 'nn_unet_workspace_bytes', 'nn_unet_create', 'nn_unet_set_params',
            'nn_unet_get_params', 'nn_unet_get_grads', 'nn_unet_forward', 'nn_unet_backward', 'nn_unet_adam', 'nn_unet_clip_grad_norm',
@@ -105,6 +106,7 @@ def load_library(path=LIB_PATH):
     lib.lbm_refine_create.argtypes = [vp, vp, ip, i, i, P(vp)]
     lib.lbm_refine_prolong.argtypes = [vp]
     lib.lbm_refine_step.argtypes = [vp, i]
+    lib.lbm_refine_nest.argtypes = [vp, vp]
     lib.lbm_refine_destroy.argtypes = [vp]
     lib.lbm_refine_destroy.restype = None
     lib.lbm_refine_last_error.argtypes = [vp]
@@ -439,6 +441,12 @@ class Refinement:
 
     def step(self, n=1):
         self._check(self.lib.lbm_refine_step(self.r, int(n)))
+
+    def nest(self, inner):
+        """Advance this coupling's fine level through `inner` (a Refinement whose coarse solver is
+        this one's fine solver); step the outermost coupling only."""
+        self._check(self.lib.lbm_refine_nest(self.r, inner.r))
+        self.inner = inner
 
     def residual(self):
         """Coarse residual of the last coupled step (restriction included)."""

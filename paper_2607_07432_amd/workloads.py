@@ -356,6 +356,39 @@ def refined_sphere(nx=48, ny=32, nz=32, origin=(10, 6, 6), block=(20, 20, 20), d
     return coarse, fine, tuple(origin)
 
 
+def nested_cylinder(nx=64, ny=40, origins=((14, 8), (6, 6)), blocks=((28, 24), (22, 18)), diameter=2.5,
+                    center=(14 + (6 + 11.15) / 2.0, 8 + (6 + 9.1) / 2.0), mach=0.2, reynolds=40.0,
+                    T_wall_ratio=None, bc='inflow_outflow', method=METHOD_FODIBM_R, steps=1):
+    """2D cylinder of `diameter` level-0 cells at level-0 position `center` inside nested refined
+    blocks: block k (k = 1 .. L) has blocks[k-1] cells of level k-1 at level k-1 node
+    origins[k-1] and twice its resolution; the body is on the finest level (2^L diameter nodes
+    across, about one marker per node of perimeter). Re on the diameter; the free-stream
+    temperature is chosen for the finest level. Returns (cases, origins): cases[0] is the coarse
+    grid without body, cases[k] level k (mu and lambda 2^k times the coarse ones, periodic), the
+    markers of the last in its own lattice units."""
+    L = len(blocks)
+    scale = 2 ** L
+    T_inf, T_w, kind, tv = _refined_temperatures(mach, reynolds, scale * diameter, T_wall_ratio)
+    u, mu, lam = flow_units(mach, reynolds, diameter, T_inf)
+    cases = [Case(name='nested_cylinder_0', dim=2, dims=(nx, ny), mu=mu, lam=lam, u_inf=(u, 0.0), T_inf=T_inf,
+                  bc=bc, method=method, ref_len=diameter, ref_area=diameter, surface=math.pi * diameter,
+                  T_wall=T_w, steps=steps)]
+    c = tuple(center)
+    for k in range(1, L + 1):
+        c = tuple(2.0 * (c[a] - origins[k - 1][a]) for a in range(2))
+        f = 2 ** k
+        dk = f * diameter
+        case = Case(name=f'nested_cylinder_{k}', dim=2, dims=(2 * blocks[k - 1][0], 2 * blocks[k - 1][1]), mu=f * mu,
+                    lam=f * lam, u_inf=(u, 0.0), T_inf=T_inf, bc='periodic', method=method, ref_len=dk, ref_area=dk,
+                    surface=math.pi * dk, T_wall=T_w, steps=steps)
+        if k == L:
+            X, n = cylinder_markers(c, dk / 2.0, int(round(math.pi * dk)))
+            for key, v in _markers_common(X, n, kind, tv).items():
+                setattr(case, key, v)
+        cases.append(case)
+    return cases, tuple(tuple(o) for o in origins)
+
+
 def acoustic_pulse(nx=160, ny=4, u_inf=0.1, amp=1e-3, x0=60.0, width=6.0, mu=0.005, bc='characteristic',
                    sigma_c=0.0):
     """A plane right-running isentropic pressure pulse on a stream along x (2D, no body, periodic
