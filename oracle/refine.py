@@ -37,7 +37,7 @@ from oracle import lbm as L
 class Block:
     origin: tuple   # coarse node of fine node 0, per axis (x, y[, z])
     size: tuple     # extent in coarse cells per axis: the fine grid has 2 size[a] nodes on axis a
-    G: int = 4      # band refilled from the coarse grid (fine nodes)
+    G: int = 2      # band refilled from the coarse grid (fine nodes; two cover one fine step's reach)
     R: int = 8      # restriction margin (fine nodes)
 
     @property

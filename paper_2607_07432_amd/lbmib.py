@@ -415,12 +415,13 @@ class Batch:
 
 
 class Refinement:
-    """A fine Solver embedded in a coarse Solver (two-level grid, ratio 2; lbm_refine_* of the C ABI).
+    """A fine Solver embedded in a coarse Solver (ratio 2; lbm_refine_* of the C ABI); couplings
+    nest through `nest`.
 
     origin: coarse node of fine node 0 per axis (x, y[, z]). The fine solver must have been created
     with twice the coarse mu and lambda_ and periodic closure (fine_params_for builds them)."""
 
-    def __init__(self, coarse, fine, origin, band=4, margin=8):
+    def __init__(self, coarse, fine, origin, band=2, margin=8):
         self.lib = load_library()
         self.coarse, self.fine = coarse, fine
         org = np.ascontiguousarray(list(origin) + [0] * (3 - len(origin)), dtype=np.int32)
