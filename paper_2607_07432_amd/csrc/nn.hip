@@ -114,16 +114,15 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
         }
 }
 
-// Convolution forward (3x3) with the input staged through LDS. A workgroup of 4 wavefronts owns
-// COB output channels x CONV_NPX (64 or 128) pixels, the pixels being a TH x TW block of one image
-// (TW = min(64, W), TH = CONV_NPX / TW, rows beyond the image masked). Per chunk of 32 input channels it stages the
-// (TH + 2) x (TW + 2) input block with its one-pixel halo (zero outside the image) as 16-byte
-// vectors into LDS ([pixel][channel], padded), then runs the nine taps from there: the B operand
-// of tap (dy, dx) for output pixel (ty, tx) is the staged pixel (ty + dy + 1, tx + dx + 1), so
-// every input value is read from memory once per chunk instead of once per tap. The A operand
-// (weights) is read from global memory as in k_conv_fwd when COB = 64 (two wavefronts share each
-// weight row); with COB = 32 all four wavefronts need the same weights, so the chunk's weights of
-// all nine taps are staged in LDS too ([tap][channel][32 + 8]) and read from there. Wavefront w
+// Convolution forward (3x3) with the input and the weights staged through LDS. A workgroup of 4
+// wavefronts owns COB output channels x CONV_NPX (64 or 128) pixels, the pixels being a TH x TW
+// block of one image (TW = min(64, W), TH = CONV_NPX / TW, rows beyond the image masked). Per chunk
+// of 32 input channels it stages the (TH + 2) x (TW + 2) input block with its one-pixel halo (zero
+// outside the image) and the chunk's weights of all nine taps ([tap][channel][32 + 8]) as 16-byte
+// vectors into LDS, then runs the nine taps from there: the B operand of tap (dy, dx) for output
+// pixel (ty, tx) is the staged pixel (ty + dy + 1, tx + dx + 1), so every input value and weight
+// is read from memory once per chunk. The global loads of the next chunk are issued into
+// registers before the MFMAs of the current one and stored into LDS after them. Wavefront w
 // computes 32 channels x (CONV_NPX / WN) pixels with WM = COB / 32 wavefronts along the channels.
 // Requires cin % 32 == 0, cout % COB == 0, xstride % 8 == 0, ystride, yoff % 4 == 0.
 template <int COB, int CONV_NPX>
@@ -134,11 +133,12 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__
     constexpr int CK = 32, LDP = CK + 8;
     constexpr int MAXP = (CONV_NPX / 64 + 2) * 66;  // largest staged block: TW = 64
     constexpr int WM = COB / 32, WN = 4 / WM, TNW = CONV_NPX / (16 * WN);
-    constexpr bool WST = COB == 32;                 // weights staged in LDS
+    constexpr int PV = (MAXP * (CK / 8) + 255) / 256;        // input vectors per thread and chunk (bound)
+    constexpr int NWV = 9 * COB * (CK / 8), WV = (NWV + 255) / 256;   // weight vectors
     __shared__ __bf16 patch[MAXP * LDP];
-    __shared__ __bf16 wst[WST ? 9 * COB * LDP : 1];
+    __shared__ __bf16 wst[9 * COB * LDP];
     const int th = CONV_NPX / tw;
-    const int pw = tw + 2, np = (th + 2) * pw;
+    const int pw = tw + 2, np = (th + 2) * pw, npv = np * (CK / 8);
     const int co_tiles = cout / COB;
     const int bx_tiles = Wd / tw, by_tiles = (H + th - 1) / th;
     long long b = blockIdx.x;
@@ -151,7 +151,6 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__
     const int x0 = bxt * tw, y0 = byt * th;
     const int t = threadIdx.x, lane = t % WAVE, wv = t / WAVE;
     const int wm = wv / WN, wn = wv % WN;
-    const int co_w = cot * COB + wm * 32;
     const int K = 9 * cin;
     const long long img = n * H * Wd;
 
@@ -170,37 +169,57 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__
     const bf16x8 zero = {};
     const int kg = 8 * (lane / 16);                 // this lane's 8-channel group within a k step
 
-    for (int ci0 = 0; ci0 < cin; ci0 += CK) {
-        __syncthreads();                            // the previous chunk's reads are done
-        for (int v = t; v < np * (CK / 8); v += 256) {
-            const int pix = v / (CK / 8), g = v % (CK / 8);
-            const int y = y0 - 1 + pix / pw, x = x0 - 1 + pix % pw;
-            bf16x8 val = zero;
-            if (y >= 0 && y < H && x >= 0 && x < Wd)
-                val = *reinterpret_cast<const bf16x8*>(X + (img + (long long)y * Wd + x) * xstride + ci0 + 8 * g);
-            *reinterpret_cast<bf16x8*>(patch + pix * LDP + 8 * g) = val;
-        }
-        if constexpr (WST) {
-            for (int v = t; v < 9 * COB * (CK / 8); v += 256) {
-                const int g = v % (CK / 8), row = v / (CK / 8);      // row = tap * COB + channel
-                const int tap = row / COB, co = row % COB;
-                *reinterpret_cast<bf16x8*>(wst + row * LDP + 8 * g) = *reinterpret_cast<const bf16x8*>(
-                    Wt + (long long)(cot * COB + co) * K + (long long)tap * cin + ci0 + 8 * g);
+    bf16x8 pr[PV], wr[WV];
+    auto fetch = [&](int ci0) {
+#pragma unroll
+        for (int r = 0; r < PV; ++r) {
+            const int v = t + 256 * r;
+            pr[r] = zero;
+            if (v < npv) {
+                const int pix = v / (CK / 8), g = v % (CK / 8);
+                const int y = y0 - 1 + pix / pw, x = x0 - 1 + pix % pw;
+                if (y >= 0 && y < H && x >= 0 && x < Wd)
+                    pr[r] = *reinterpret_cast<const bf16x8*>(X + (img + (long long)y * Wd + x) * xstride + ci0 + 8 * g);
             }
         }
+#pragma unroll
+        for (int r = 0; r < WV; ++r) {
+            const int v = t + 256 * r;
+            wr[r] = zero;
+            if (v < NWV) {
+                const int g = v % (CK / 8), row = v / (CK / 8);      // row = tap * COB + channel
+                const int tap = row / COB, co = row % COB;
+                wr[r] = *reinterpret_cast<const bf16x8*>(Wt + (long long)(cot * COB + co) * K + (long long)tap * cin +
+                                                         ci0 + 8 * g);
+            }
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int r = 0; r < PV; ++r) {
+            const int v = t + 256 * r;
+            if (v < npv) *reinterpret_cast<bf16x8*>(patch + (v / (CK / 8)) * LDP + 8 * (v % (CK / 8))) = pr[r];
+        }
+#pragma unroll
+        for (int r = 0; r < WV; ++r) {
+            const int v = t + 256 * r;
+            if (v < NWV) *reinterpret_cast<bf16x8*>(wst + (v / (CK / 8)) * LDP + 8 * (v % (CK / 8))) = wr[r];
+        }
+    };
+
+    fetch(0);
+    for (int ci0 = 0; ci0 < cin; ci0 += CK) {
+        __syncthreads();                            // the previous chunk's reads are done
+        stash();
         __syncthreads();
+        if (ci0 + CK < cin) fetch(ci0 + CK);        // in flight during this chunk's MFMAs
 #pragma unroll 3
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap % 3;   // offsets + 1
-            const long long kk = (long long)tap * cin + ci0 + kg;
             bf16x8 a[2], bv[TNW];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                if constexpr (WST)
-                    a[i] = *reinterpret_cast<const bf16x8*>(wst + (tap * COB + wm * 32 + i * 16 + lane % 16) * LDP + kg);
-                else
-                    a[i] = *reinterpret_cast<const bf16x8*>(Wt + (long long)(co_w + i * 16 + lane % 16) * K + kk);
-            }
+            for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(wst + (tap * COB + wm * 32 + i * 16 + lane % 16) * LDP + kg);
 #pragma unroll
             for (int j = 0; j < TNW; ++j)
                 bv[j] = *reinterpret_cast<const bf16x8*>(patch + ((tyj[j] + dy) * pw + txj[j] + dx) * LDP + kg);
@@ -211,6 +230,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bv[j], acc[i][j], 0, 0, 0);
         }
     }
+    const int co_w = cot * COB + wm * 32;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
