@@ -40,12 +40,12 @@ constexpr int CH[LEVELS] = {32, 64, 128, 256, 256};
 // A lane l holds W[co][k .. k+7] with co = l % 16, k = 8 (l / 16) + 32 s; B lane l holds
 // X[pixel l % 16][k .. k+7]; the result lane l holds rows 4 (l / 16) + r of column l % 16.
 // X has pixel stride xstride; Y is written at Y[p ystride + yoff + co].
-// Requires cin, xstride % 8 == 0, cout % (16 TM) == 0, ystride, yoff % 4 == 0.
+// gate: as in k_conv_fwd_lds. Requires cin, xstride % 8 == 0, cout % (16 TM) == 0, ystride, yoff % 4 == 0.
 template <int TM, int TN>
 __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, int cin, int xstride,
                                                   const __bf16* __restrict__ Wt, const float* __restrict__ bias, int cout,
                                                   int taps, int H, int Wd, long long P, int relu, __bf16* __restrict__ Y,
-                                                  int ystride, int yoff) {
+                                                  int ystride, int yoff, const __bf16* __restrict__ gate) {
     const int lane = threadIdx.x % WAVE;
     const long long wave = (long long)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int co_tiles = cout / (16 * TM);
@@ -103,11 +103,13 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
             if (!pv[j]) continue;
             const int cb = co0 + i * 16 + (lane / 16) * 4;
             const long long p = p0 + j * 16 + lane % 16;
-            bf16x4 o;
+            bf16x4 o, gv = {};
+            if (gate) gv = *reinterpret_cast<const bf16x4*>(gate + p * ystride + yoff + cb);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 float v = acc[i][j][r] + (bias ? bias[cb + r] : 0.f);
                 if (relu) v = v > 0.f ? v : 0.f;
+                if (gate && !((float)gv[r] > 0.f)) v = 0.f;
                 o[r] = (__bf16)v;
             }
             *reinterpret_cast<bf16x4*>(Y + p * ystride + yoff + cb) = o;
@@ -124,12 +126,15 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
 // is read from memory once per chunk. The global loads of the next chunk are issued into
 // registers before the MFMAs of the current one and stored into LDS after them. Wavefront w
 // computes 32 channels x (CONV_NPX / WN) pixels with WM = COB / 32 wavefronts along the channels.
-// Requires cin % 32 == 0, cout % COB == 0, xstride % 8 == 0, ystride, yoff % 4 == 0.
+// With gate (same layout as Y), the output is zeroed where gate is not positive (the backward of
+// a ReLU whose output gate is). Requires cin % 32 == 0, cout % COB == 0, xstride % 8 == 0,
+// ystride, yoff % 4 == 0.
 template <int COB, int CONV_NPX>
 __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__ X, int cin, int xstride,
                                                       const __bf16* __restrict__ Wt, const float* __restrict__ bias,
                                                       int cout, int H, int Wd, int tw, int relu,
-                                                      __bf16* __restrict__ Y, int ystride, int yoff) {
+                                                      __bf16* __restrict__ Y, int ystride, int yoff,
+                                                      const __bf16* __restrict__ gate) {
     constexpr int CK = 32, LDP = CK + 8;
     constexpr int MAXP = (CONV_NPX / 64 + 2) * 66;  // largest staged block: TW = 64
     constexpr int WM = COB / 32, WN = 4 / WM, TNW = CONV_NPX / (16 * WN);
@@ -239,11 +244,13 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__
             if (y >= H) continue;
             const long long p = img + (long long)y * Wd + x0 + txj[j];
             const int cb = co_w + i * 16 + (lane / 16) * 4;
-            bf16x4 o;
+            bf16x4 o, gv = {};
+            if (gate) gv = *reinterpret_cast<const bf16x4*>(gate + p * ystride + yoff + cb);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 float v = acc[i][j][r] + (bias ? bias[cb + r] : 0.f);
                 if (relu) v = v > 0.f ? v : 0.f;
+                if (gate && !((float)gv[r] > 0.f)) v = 0.f;
                 o[r] = (__bf16)v;
             }
             *reinterpret_cast<bf16x4*>(Y + p * ystride + yoff + cb) = o;
@@ -546,31 +553,26 @@ __global__ void k_sum_splits(const float* __restrict__ part, int nsplit, long lo
     g[i] = strided_sum8(part, nsplit, n, i);
 }
 
-// W'[ci][8 - t][co] = W[co][t][ci]: backward data is the forward convolution of dY with W'.
-__global__ void k_flip(const __bf16* __restrict__ W, int cout, int cin, __bf16* __restrict__ Wf) {
+// W'[ci][8 - t][co] = W[co][t][ci] for every 3x3 layer at once (backward data is the forward
+// convolution of dY with W'); the flipped copy of a layer sits at the layer's bf16 offset.
+constexpr int FLIP_MAXL = 24;
+struct FlipTab {
+    int n;                              // layers (3x3, in offset order)
+    long long total;                    // weights in all of them
+    long long off[FLIP_MAXL];           // bf16 offset of each layer
+    int cout[FLIP_MAXL], cin[FLIP_MAXL];
+};
+__global__ void k_flip_all(const __bf16* __restrict__ W, FlipTab tab, __bf16* __restrict__ Wf) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long n = (long long)cout * 9 * cin;
-    if (i >= n) return;
-    const int ci = (int)(i % cin);
-    const int t = (int)((i / cin) % 9);
-    const int co = (int)(i / (9LL * cin));
-    Wf[((long long)ci * 9 + (8 - t)) * cout + co] = W[i];
-}
-
-// dA[p][off + c] *= (A[p][off + c] > 0), c < C (in place on the gradient of a ReLU output).
-// One thread per 8 channels (C, stride and off multiples of 8).
-__global__ void k_relu_bwd(__bf16* __restrict__ dA, const __bf16* __restrict__ A, long long P, int C, int stride, int off) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int G = C / 8;
-    if (i >= P * G) return;
-    const long long p = i / G;
-    const long long o = p * stride + off + 8 * (int)(i - p * G);
-    const bf16x8 a = *reinterpret_cast<const bf16x8*>(A + o);
-    bf16x8 g = *reinterpret_cast<const bf16x8*>(dA + o);
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-        if (!((float)a[k] > 0.f)) g[k] = (__bf16)0.f;
-    *reinterpret_cast<bf16x8*>(dA + o) = g;
+    if (i >= tab.total) return;
+    int l = 0;
+    while (l + 1 < tab.n && i >= tab.off[l + 1]) ++l;
+    const long long o = i - tab.off[l];
+    const int cin = tab.cin[l], cout = tab.cout[l];
+    const int ci = (int)(o % cin);
+    const int t = (int)((o / cin) % 9);
+    const int co = (int)(o / (9LL * cin));
+    Wf[tab.off[l] + ((long long)ci * 9 + (8 - t)) * cout + co] = W[i];
 }
 
 // 2x2 average pooling of a channel slice: out[n][y][x][c] = mean of in[n][2y+i][2x+j][off + c].
@@ -597,9 +599,10 @@ __global__ void k_pool(const __bf16* __restrict__ in, int stride, int off, int C
     *reinterpret_cast<bf16x8*>(out + q * C + c) = o;
 }
 
-// Adjoint of the pooling, accumulated: dIn[n][2y+i][2x+j][off + c] += dOut[n][y][x][c] / 4.
+// Adjoint of the pooling, accumulated: dIn[n][2y+i][2x+j][off + c] += dOut[n][y][x][c] / 4, then
+// zeroed where gate (the ReLU output, same layout as dIn) is not positive.
 __global__ void k_pool_bwd(const __bf16* __restrict__ dOut, int C, int B, int H, int Wd, __bf16* __restrict__ dIn,
-                           int stride, int off) {
+                           int stride, int off, const __bf16* __restrict__ gate) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int G = C / 8;
     const long long n_in = (long long)B * H * Wd * G;
@@ -611,8 +614,12 @@ __global__ void k_pool_bwd(const __bf16* __restrict__ dOut, int C, int B, int H,
     const bf16x8 g = *reinterpret_cast<const bf16x8*>(dOut + ((n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c);
     const long long o = q * stride + off + c;
     bf16x8 d = *reinterpret_cast<const bf16x8*>(dIn + o);
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(gate + o);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) d[k] = (__bf16)((float)d[k] + 0.25f * (float)g[k]);
+    for (int k = 0; k < 8; ++k) {
+        d[k] = (__bf16)((float)d[k] + 0.25f * (float)g[k]);
+        if (!((float)a[k] > 0.f)) d[k] = (__bf16)0.f;
+    }
     *reinterpret_cast<bf16x8*>(dIn + o) = d;
 }
 
@@ -631,9 +638,10 @@ __global__ void k_up(const __bf16* __restrict__ in, int C, int B, int H, int Wd,
         *reinterpret_cast<const bf16x8*>(in + ((n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c);
 }
 
-// Adjoint of the upsampling: dIn[n][y][x][c] = sum of the four dOut[n][2y+i][2x+j][off + c].
+// Adjoint of the upsampling: dIn[n][y][x][c] = sum of the four dOut[n][2y+i][2x+j][off + c],
+// zeroed where gate (the ReLU output, layout of dIn) is not positive.
 __global__ void k_up_bwd(const __bf16* __restrict__ dOut, int stride, int off, int C, int B, int H, int Wd,
-                         __bf16* __restrict__ dIn) {
+                         __bf16* __restrict__ dIn, const __bf16* __restrict__ gate) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int h = H / 2, w = Wd / 2, G = C / 8;
     const long long n_in = (long long)B * h * w * G;
@@ -647,9 +655,13 @@ __global__ void k_up_bwd(const __bf16* __restrict__ dOut, int stride, int off, i
     const bf16x8 v1 = *reinterpret_cast<const bf16x8*>(dOut + b + stride);
     const bf16x8 v2 = *reinterpret_cast<const bf16x8*>(dOut + b + (long long)Wd * stride);
     const bf16x8 v3 = *reinterpret_cast<const bf16x8*>(dOut + b + (long long)Wd * stride + stride);
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(gate + q * C + c);
     bf16x8 o;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) o[k] = (__bf16)(((float)v0[k] + (float)v1[k]) + ((float)v2[k] + (float)v3[k]));
+    for (int k = 0; k < 8; ++k) {
+        o[k] = (__bf16)(((float)v0[k] + (float)v1[k]) + ((float)v2[k] + (float)v3[k]));
+        if (!((float)a[k] > 0.f)) o[k] = (__bf16)0.f;
+    }
     *reinterpret_cast<bf16x8*>(dIn + q * C + c) = o;
 }
 
@@ -679,9 +691,10 @@ __global__ void k_head_fwd(const __bf16* __restrict__ A, const float* __restrict
     }
 }
 
-// Head backward, data: dA[p][c] = sum_o Wh[o][c] dOut[p][o] (bf16).
+// Head backward, data: dA[p][c] = sum_o Wh[o][c] dOut[p][o] (bf16), zeroed where gate[p][c] (the
+// ReLU output the head reads) is not positive.
 __global__ void k_head_dgrad(const float* __restrict__ Wh, const float* __restrict__ dOut, long long P,
-                             __bf16* __restrict__ dA) {
+                             __bf16* __restrict__ dA, const __bf16* __restrict__ gate) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     float g[NOUT];
@@ -692,7 +705,7 @@ __global__ void k_head_dgrad(const float* __restrict__ Wh, const float* __restri
         float s = 0.f;
 #pragma unroll
         for (int o = 0; o < NOUT; ++o) s += Wh[o * 32 + c] * g[o];
-        dA[p * 32 + c] = (__bf16)s;
+        dA[p * 32 + c] = (float)gate[p * 32 + c] > 0.f ? (__bf16)s : (__bf16)0.f;
     }
 }
 
@@ -930,7 +943,8 @@ struct nn_unet {
     long long np = 0, nbf = 0;
     float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
     __bf16* wbf = nullptr;          // bf16 weights, concatenated per layer
-    __bf16* wflip = nullptr;        // flipped weights of one layer (backward data)
+    __bf16* wflip = nullptr;        // flipped bf16 weights of every 3x3 layer (backward data), as wbf
+    FlipTab ftab{};
     long long* bf_map = nullptr;    // parameter index -> bf16 index or -1
     float* split = nullptr;         // weight-gradient split partials
     size_t split_floats = 0;
@@ -985,7 +999,7 @@ size_t layout(nn_unet* u, int B, int H, int W, char* base) {
     __bf16* wbf = (__bf16*)take(nbf * 2);
     long long maxw = 0;
     for (auto& x : L) maxw = std::max(maxw, (long long)x.cout * x.taps * x.cin);
-    __bf16* wflip = (__bf16*)take(maxw * 2);
+    __bf16* wflip = (__bf16*)take(nbf * 2);
     long long* bf_map = (long long*)take(np * 8);
     // split partials: at most 64 splits of the largest weight
     const size_t split_floats = (size_t)64 * maxw;
@@ -1057,7 +1071,7 @@ int dec_conv(int l, int k) { return 2 * LEVELS + 2 * (LEVELS - 2 - l) + k; }
 int head_layer() { return 2 * LEVELS + 2 * (LEVELS - 1); }
 
 hipError_t conv_fwd(nn_unet* u, const Layer& ly, const __bf16* X, int xstride, const __bf16* Wt, const float* bias,
-                    int relu, int B, int H, int W, __bf16* Y, int ystride, int yoff) {
+                    int relu, int B, int H, int W, __bf16* Y, int ystride, int yoff, const __bf16* gate = nullptr) {
     const long long P = (long long)B * H * W;
     // 3x3 layers with 32-channel multiples and power-of-two widths: input staged through LDS
     if (ly.taps == 9 && ly.cin % 32 == 0 && ly.cout % 32 == 0 && xstride % 8 == 0 && ystride % 4 == 0 &&
@@ -1071,23 +1085,23 @@ hipError_t conv_fwd(nn_unet* u, const Layer& ly, const __bf16* X, int xstride, c
         const unsigned nblk = (unsigned)((long long)B * ((H + th - 1) / th) * (W / tw) * (ly.cout / cob));
         if (cob == 64 && npx == 128)
             hipLaunchKernelGGL((k_conv_fwd_lds<64, 128>), dim3(nblk), dim3(256), 0, u->stream, X, ly.cin, xstride, Wt,
-                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
+                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff, gate);
         else if (cob == 64)
             hipLaunchKernelGGL((k_conv_fwd_lds<64, 64>), dim3(nblk), dim3(256), 0, u->stream, X, ly.cin, xstride, Wt,
-                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
+                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff, gate);
         else if (npx == 128)
             hipLaunchKernelGGL((k_conv_fwd_lds<32, 128>), dim3(nblk), dim3(256), 0, u->stream, X, ly.cin, xstride, Wt,
-                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
+                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff, gate);
         else
             hipLaunchKernelGGL((k_conv_fwd_lds<32, 64>), dim3(nblk), dim3(256), 0, u->stream, X, ly.cin, xstride, Wt,
-                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff);
+                               bias, ly.cout, H, W, tw, relu, Y, ystride, yoff, gate);
         return hipGetLastError();
     }
     constexpr int TM = 2, TN = 4;
     if (ly.cout % (16 * TM) || ly.cin % 8 || xstride % 8 || ystride % 4 || yoff % 4) return hipErrorInvalidValue;
     const long long tiles = (long long)(ly.cout / (16 * TM)) * ((P + 16 * TN - 1) / (16 * TN));
     hipLaunchKernelGGL((k_conv_fwd<TM, TN>), dim3(blocks(tiles, 4)), dim3(256), 0, u->stream, X, ly.cin, xstride, Wt,
-                       bias, ly.cout, ly.taps, H, W, P, relu, Y, ystride, yoff);
+                       bias, ly.cout, ly.taps, H, W, P, relu, Y, ystride, yoff, gate);
     return hipGetLastError();
 }
 
@@ -1145,17 +1159,16 @@ hipError_t conv_wgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, co
 
 // dX [P][cin] (stride dxs) of a 3x3 layer from dY (stride dys): forward convolution with the
 // flipped weights.
-hipError_t conv_dgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, int B, int H, int W, __bf16* dX, int dxs) {
-    const long long n = (long long)ly.cout * 9 * ly.cin;
-    hipLaunchKernelGGL(k_flip, dim3(blocks(n)), dim3(256), 0, u->stream, (const __bf16*)(u->wbf + ly.bf_off), ly.cout,
-                       ly.cin, u->wflip);
+hipError_t conv_dgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, int B, int H, int W, __bf16* dX, int dxs,
+                      const __bf16* gate = nullptr) {
     Layer t{ly.cout, ly.cin, 9, 0, 0, 0};
-    return conv_fwd(u, t, dY, dys, u->wflip, nullptr, 0, B, H, W, dX, dxs, 0);
+    return conv_fwd(u, t, dY, dys, u->wflip + ly.bf_off, nullptr, 0, B, H, W, dX, dxs, 0, gate);
 }
 
-hipError_t relu_bwd(nn_unet* u, __bf16* g, const __bf16* a, long long P, int C, int stride, int off) {
-    if (C % 8 || stride % 8 || off % 8) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks(P * C / 8)), dim3(256), 0, u->stream, g, a, P, C, stride, off);
+// Refresh the flipped weights after the bf16 copy changed (set_params, Adam).
+hipError_t flip_weights(nn_unet* u) {
+    hipLaunchKernelGGL(k_flip_all, dim3(blocks(u->ftab.total)), dim3(256), 0, u->stream, (const __bf16*)u->wbf, u->ftab,
+                       u->wflip);
     return hipGetLastError();
 }
 
@@ -1226,7 +1239,7 @@ int backward(nn_unet* u, const float* d_tgt, const float* d_mask, double* d_loss
     const Layer& hd = u->L[head_layer()];
     const int nh = (int)((P0 + HEAD_PIX - 1) / HEAD_PIX);
     hipLaunchKernelGGL(k_head_dgrad, dim3(blocks(P0)), dim3(256), 0, u->stream, (const float*)(u->theta + hd.w_off),
-                       (const float*)u->dout, P0, u->dec_b[0].g);
+                       (const float*)u->dout, P0, u->dec_b[0].g, (const __bf16*)u->dec_b[0].a);
     hipLaunchKernelGGL(k_head_wgrad, dim3(nh), dim3(256), 0, u->stream, (const __bf16*)u->dec_b[0].a,
                        (const float*)u->dout, P0, u->small);
     hipLaunchKernelGGL(k_colsum, dim3(HEAD_NP), dim3(256), 0, u->stream, (const float*)u->small, nh, HEAD_NP,
@@ -1238,17 +1251,18 @@ int backward(nn_unet* u, const float* d_tgt, const float* d_mask, double* d_loss
         const long long P = (long long)B * h * w;
         const Layer& d0 = u->L[dec_conv(l, 0)];
         const Layer& d1 = u->L[dec_conv(l, 1)];
-        NCHK(u, relu_bwd(u, u->dec_b[l].g, u->dec_b[l].a, P, CH[l], CH[l], 0));
+        // the gradients of ReLU outputs arrive gated by their producers (head, upsampling adjoint,
+        // backward-data epilogue, pooling adjoint)
         NCHK(u, conv_wgrad(u, d1, u->dec_b[l].g, CH[l], u->dec_a[l].a, CH[l], B, h, w));
-        NCHK(u, conv_dgrad(u, d1, u->dec_b[l].g, CH[l], B, h, w, u->dec_a[l].g, CH[l]));
-        NCHK(u, relu_bwd(u, u->dec_a[l].g, u->dec_a[l].a, P, CH[l], CH[l], 0));
+        NCHK(u, conv_dgrad(u, d1, u->dec_b[l].g, CH[l], B, h, w, u->dec_a[l].g, CH[l], u->dec_a[l].a));
         NCHK(u, conv_wgrad(u, d0, u->dec_a[l].g, CH[l], u->cat[l].a, u->cat[l].c, B, h, w));
         NCHK(u, conv_dgrad(u, d0, u->dec_a[l].g, CH[l], B, h, w, u->cat[l].g, u->cat[l].c));
         // the upsampled part of the concatenation goes to the output of the level below
         __bf16* gbelow = l + 1 < LEVELS - 1 ? u->dec_b[l + 1].g : u->bott_b.g;
+        const __bf16* abelow = l + 1 < LEVELS - 1 ? u->dec_b[l + 1].a : u->bott_b.a;
         const long long n = (long long)B * (h / 2) * (w / 2) * CH[l + 1];
         hipLaunchKernelGGL(k_up_bwd, dim3(blocks(n / 8)), dim3(256), 0, u->stream, (const __bf16*)u->cat[l].g, u->cat[l].c, 0,
-                           CH[l + 1], B, h, w, gbelow);
+                           CH[l + 1], B, h, w, gbelow, abelow);
         NCHK(u, hipGetLastError());
     }
     // bottleneck and encoder, deepest level first
@@ -1272,13 +1286,11 @@ int backward(nn_unet* u, const float* d_tgt, const float* d_mask, double* d_loss
             off = CH[l + 1];
             const long long n = P * CH[l];
             hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(n / 8)), dim3(256), 0, u->stream, (const __bf16*)u->pool[l + 1].g,
-                               CH[l], B, h, w, ga, stride, off);
+                               CH[l], B, h, w, ga, stride, off, (const __bf16*)aa);
             NCHK(u, hipGetLastError());
         }
-        NCHK(u, relu_bwd(u, ga, aa, P, CH[l], stride, off));
         NCHK(u, conv_wgrad(u, c1, ga + off, stride, u->enc_a[l].a, CH[l], B, h, w));
-        NCHK(u, conv_dgrad(u, c1, ga + off, stride, B, h, w, u->enc_a[l].g, CH[l]));
-        NCHK(u, relu_bwd(u, u->enc_a[l].g, u->enc_a[l].a, P, CH[l], CH[l], 0));
+        NCHK(u, conv_dgrad(u, c1, ga + off, stride, B, h, w, u->enc_a[l].g, CH[l], u->enc_a[l].a));
         const __bf16* xin = l > 0 ? u->pool[l].a : u->in0;
         const int xs = l > 0 ? CH[l - 1] : CIN0;
         NCHK(u, conv_wgrad(u, c0, u->enc_a[l].g, CH[l], xin, xs, B, h, w));
@@ -1319,10 +1331,25 @@ int nn_unet_create(int batch, int H, int W, void* ws, size_t bytes, void* stream
         const long long n = (long long)x.cout * x.taps * x.cin;
         for (long long k = 0; k < n; ++k) map[x.w_off + k] = x.bf_off + k;
     }
+    u->ftab.n = 0;
+    for (size_t i = 0; i < u->L.size(); ++i) {
+        const Layer& x = u->L[i];
+        if (x.taps != 9) continue;
+        if (u->ftab.n == FLIP_MAXL) {
+            delete u;
+            return nfail(nullptr, NN_E_INVAL, "too many layers for the flip table");
+        }
+        u->ftab.off[u->ftab.n] = x.bf_off;
+        u->ftab.cout[u->ftab.n] = x.cout;
+        u->ftab.cin[u->ftab.n] = x.cin;
+        u->ftab.total = x.bf_off + (long long)x.cout * 9 * x.cin;   // the 3x3 layers come first and are contiguous
+        ++u->ftab.n;
+    }
     hipError_t e = hipMemcpy(u->bf_map, map.data(), map.size() * 8, hipMemcpyHostToDevice);
     for (float* a : {u->theta, u->m, u->v, u->grad})
         if (e == hipSuccess) e = hipMemsetAsync(a, 0, u->np * 4, u->stream);
     if (e == hipSuccess) e = hipMemsetAsync(u->wbf, 0, u->nbf * 2, u->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(u->wflip, 0, u->nbf * 2, u->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(u->stream);
     if (e != hipSuccess) {
         std::string m = hipGetErrorString(e);
@@ -1342,6 +1369,7 @@ int nn_unet_set_params(nn_unet* u, const float* params, int on_device) {
     hipLaunchKernelGGL(k_to_bf, dim3(blocks(u->np)), dim3(256), 0, u->stream, (const float*)u->theta, u->np,
                        (const long long*)u->bf_map, u->wbf);
     NCHK(u, hipGetLastError());
+    NCHK(u, flip_weights(u));
     if (!on_device) NCHK(u, hipStreamSynchronize(u->stream));
     return NN_OK;
 }
@@ -1381,6 +1409,7 @@ int nn_unet_adam(nn_unet* u, double lr, double beta1, double beta2, double eps, 
                        u->np, (float)lr, (float)beta1, (float)beta2, (float)eps, c1, c2, (float)weight_decay,
                        (const long long*)u->bf_map, u->wbf);
     NCHK(u, hipGetLastError());
+    NCHK(u, flip_weights(u));
     return NN_OK;
 }
 
