@@ -389,7 +389,8 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_lds(const __bf16* __restrict
 
 // Weight and bias gradients, deeper steps: as k_conv_wgrad_lds, but each barrier pair covers KP
 // pixels (KP / 32 MFMA steps per 16 x 16 sub-tile) and every thread stages several 8-channel
-// vectors of each operand. Requires W % KP == 0 and splits of a multiple of KP pixels. The bias gradient (row sums of dY over the pixels) comes from the
+// vectors of each operand. Requires KP to divide H W, W and KP to divide one another, and splits of
+// a multiple of KP pixels. The bias gradient (row sums of dY over the pixels) comes from the
 // same MFMA unit: the wavefronts of the first k tile multiply their dY rows by a ones operand.
 template <int BM, int KP>
 __global__ void __launch_bounds__(256) k_conv_wgrad_deep(const __bf16* __restrict__ dY, int cout, int dys,
@@ -426,16 +427,19 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_deep(const __bf16* __restric
     bf16x8 ones;
 #pragma unroll
     for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
-    // A step of KP pixels starts at a multiple of KP and W is a multiple of KP: its pixels share
-    // the image and the row, so only the step's base is divided; the channel offsets, taps and
-    // shifts of each staged vector are fixed for the whole split.
-    int b_ci[BR], b_dy[BR], b_dx[BR], b_pix[BR];
+    // A step of KP pixels starts at a multiple of KP, KP divides H W, and W and KP divide one
+    // another: the step lies in one image, within one row (W >= KP) or over whole rows (W < KP),
+    // so only the step's base is divided; the channel offsets, taps, shifts and row/column offsets
+    // of each staged vector are fixed for the whole split.
+    int b_ci[BR], b_dy[BR], b_dx[BR], b_pix[BR], b_row[BR], b_col[BR];
     bool b_on[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
         const int v_ = t + 256 * r;
         const int g = v_ / KP, k = k0 + 8 * g;
         b_pix[r] = v_ % KP;
+        b_row[r] = b_pix[r] / Wd;
+        b_col[r] = b_pix[r] - b_row[r] * Wd;
         b_on[r] = v_ < BV && k < K;
         const int tap = k / cin;
         b_ci[r] = k - tap * cin;
@@ -461,7 +465,7 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_deep(const __bf16* __restric
         for (int r = 0; r < BR; ++r) {
             vb[r] = zero;
             if (b_on[r] && q + b_pix[r] < pend) {
-                const int y = y0 + b_dy[r], x = x0 + b_pix[r] + b_dx[r];
+                const int y = y0 + b_row[r] + b_dy[r], x = x0 + b_col[r] + b_dx[r];
                 if (y >= 0 && y < H && x >= 0 && x < Wd)
                     vb[r] = *reinterpret_cast<const bf16x8*>(X + (n * HW + (long long)y * Wd + x) * xs + b_ci[r]);
             }
@@ -1105,16 +1109,17 @@ hipError_t conv_fwd(nn_unet* u, const Layer& ly, const __bf16* X, int xstride, c
     return hipGetLastError();
 }
 
-// Pixels per staging step of the weight gradient: 128 when the image width is a multiple of 128
-// and each split keeps at least two such steps (LBMIB_WGRAD_KP=32 selects the shallow kernel,
-// for comparison), else 32.
-int wgrad_kp(long long P, long long nsplit, int W) {
+// Pixels per staging step of the weight gradient: 128 when such a step lies in one image (within a
+// row, or over whole rows of a narrower level) and each split keeps at least two of them
+// (LBMIB_WGRAD_KP=32 selects the shallow kernel, for comparison), else 32.
+int wgrad_kp(long long P, long long nsplit, int H, int W) {
     static const int forced = [] {
         const char* v = std::getenv("LBMIB_WGRAD_KP");
         return v ? std::atoi(v) : 0;
     }();
     if (forced == 32) return 32;
-    return (W % 128 == 0 && P / nsplit >= 256) ? 128 : 32;
+    // W and H W are powers of two here: a 128-pixel step fits one image once H W >= 128
+    return ((long long)H * W % 128 == 0 && (W % 128 == 0 || 128 % W == 0) && P / nsplit >= 256) ? 128 : 32;
 }
 
 // dW (into grad at w_off) and db (at b_off) of a 3x3 layer from dY [P] (stride dys) and its input X.
@@ -1133,7 +1138,7 @@ hipError_t conv_wgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, co
     while ((size_t)nsplit * wsz > u->split_floats && nsplit > 1) --nsplit;
     while ((size_t)nsplit * ly.cout > u->small_floats && nsplit > 1) --nsplit;
     // deeper steps (KP pixels per barrier pair) while every split still holds two of them
-    const int KP = wgrad_kp(P, nsplit, W);
+    const int KP = wgrad_kp(P, nsplit, H, W);
     long long split_len = (P + nsplit - 1) / nsplit;
     split_len = (split_len + KP - 1) / KP * KP;
     nsplit = (P + split_len - 1) / split_len;
