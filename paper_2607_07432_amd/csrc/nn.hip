@@ -713,26 +713,54 @@ __global__ void k_head_dgrad(const float* __restrict__ Wh, const float* __restri
     }
 }
 
-// Head backward, parameters: per block of HEAD_PIX pixels, thread q < 132 sums
-// dWh[o][c] = sum_p dOut[p][o] A[p][c] (q = 32 o + c) or dbh[o] = sum_p dOut[p][o] (q = 128 + o).
+// Head backward, parameters: per block of HEAD_PIX pixels the partial sums
+// dWh[o][c] = sum_p dOut[p][o] A[p][c] (column 32 o + c) and dbh[o] = sum_p dOut[p][o] (column
+// 128 + o), each thread over a quarter of the channels of every 64th pixel, then a fixed-order tree.
 constexpr int HEAD_PIX = 256;
 constexpr int HEAD_NP = NOUT * 32 + NOUT;
 __global__ void __launch_bounds__(256) k_head_wgrad(const __bf16* __restrict__ A, const float* __restrict__ dOut,
                                                     long long P, float* __restrict__ part) {
-    const int q = threadIdx.x;
-    if (q >= HEAD_NP) return;
-    const long long p0 = (long long)blockIdx.x * HEAD_PIX;
-    const int o = q < NOUT * 32 ? q / 32 : q - NOUT * 32;
-    const int c = q < NOUT * 32 ? q % 32 : -1;
-    float s[4] = {0.f, 0.f, 0.f, 0.f};           // pixel p goes to s[p % 4], added in order
-    for (long long p = p0; p < p0 + HEAD_PIX && p < P; p += 4)
+    static_assert(NOUT == 4 && HEAD_PIX % 64 == 0, "head gradient layout");
+    __shared__ float red[64][HEAD_NP + 1];
+    // thread (g, j): channels 8 g .. 8 g + 7 of pixels j, j + 64, ... of the block (16-byte loads)
+    const int t = threadIdx.x, g = t & 3, j = t >> 2;
+    float s[NOUT][8], sb[NOUT];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (p + u >= P) break;
-            const float g = dOut[(p + u) * NOUT + o];
-            s[u] += c >= 0 ? g * (float)A[(p + u) * 32 + c] : g;
+    for (int o = 0; o < NOUT; ++o) {
+        sb[o] = 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[o][e] = 0.f;
+    }
+    const long long p0 = (long long)blockIdx.x * HEAD_PIX;
+#pragma unroll
+    for (int k = 0; k < HEAD_PIX / 64; ++k) {
+        const long long p = p0 + j + 64 * k;
+        if (p >= P) break;
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(A + p * 32 + 8 * g);
+        const float4 d = *reinterpret_cast<const float4*>(dOut + p * NOUT);
+        const float dv[NOUT] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) {
+            sb[o] += dv[o];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[o][e] += dv[o] * (float)a[e];
         }
-    part[(long long)blockIdx.x * HEAD_NP + q] = (s[0] + s[1]) + (s[2] + s[3]);
+    }
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) red[j][o * 32 + 8 * g + e] = s[o][e];
+        if (g == 0) red[j][NOUT * 32 + o] = sb[o];
+    }
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {          // fixed-order tree over the 64 pixel lanes
+        for (int idx = t; idx < w * HEAD_NP; idx += 256) {
+            const int jj = idx / HEAD_NP, q = idx - jj * HEAD_NP;
+            red[jj][q] += red[jj + w][q];
+        }
+        __syncthreads();
+    }
+    for (int q = t; q < HEAD_NP; q += 256) part[(long long)blockIdx.x * HEAD_NP + q] = red[0][q];
 }
 
 // Column sums of a [rows][n] FP32 array in fixed order: out[i] = sum_r part[r][i].
