@@ -262,13 +262,14 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const __bf16* __restrict__
 // it reads dY [32 pixels][BM channels] and X^ [32 pixels][BN columns] as 16-byte vectors of 8
 // channels, stores both transposed in LDS ([channel][pixel]) and runs one 16x16x32 MFMA per
 // 16 x 16 sub-tile: lane l reads 8 consecutive pixels of row l % 16. Each wavefront owns 32 x 32.
-// The workgroups of the first k tile also sum dY over their pixels (the bias gradient).
+// The workgroups of the first k tile also sum dY over their pixels (the bias gradient). Split s
+// writes its partials to part[s][cout K + cout]: the weights [co][k], then the biases.
 // Requires cout % BM == 0, cin % 8 == 0 and strides % 8 == 0.
 template <int BM>
 __global__ void __launch_bounds__(256) k_conv_wgrad_lds(const __bf16* __restrict__ dY, int cout, int dys,
                                                         const __bf16* __restrict__ X, int cin, int xs, int taps, int H,
                                                         int Wd, long long P, int split_len, int nsplit,
-                                                        float* __restrict__ part, float* __restrict__ bpart) {
+                                                        float* __restrict__ part) {
     constexpr int BN = 4096 / BM;
     constexpr int KP = 32, LD = KP + 8;
     __shared__ __bf16 As[BM][LD];
@@ -361,7 +362,7 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_lds(const __bf16* __restrict
             for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
-    float* out = part + (long long)s * cout * K;
+    float* out = part + (long long)s * (cout * K + cout);   // split row: weights, then biases
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -382,7 +383,7 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_lds(const __bf16* __restrict
         if (t < BM) {
             float v = 0.f;
             for (int r = 0; r < KP; ++r) v += bred[r][t];
-            bpart[(long long)s * cout + co0 + t] = v;
+            out[(long long)cout * K + co0 + t] = v;
         }
     }
 }
@@ -396,7 +397,7 @@ template <int BM, int KP>
 __global__ void __launch_bounds__(256) k_conv_wgrad_deep(const __bf16* __restrict__ dY, int cout, int dys,
                                                          const __bf16* __restrict__ X, int cin, int xs, int taps, int H,
                                                          int Wd, long long P, int split_len, int nsplit,
-                                                         float* __restrict__ part, float* __restrict__ bpart) {
+                                                         float* __restrict__ part) {
     constexpr int BN = 4096 / BM;
     constexpr int LD = KP + 8;
     constexpr int AV = BM * KP / 8, BV = BN * KP / 8;      // 8-channel vectors per step
@@ -516,7 +517,7 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_deep(const __bf16* __restric
         }
         __syncthreads();
     }
-    float* out = part + (long long)s * cout * K;
+    float* out = part + (long long)s * (cout * K + cout);   // split row: weights, then biases
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -535,7 +536,7 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_deep(const __bf16* __restric
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                bpart[(long long)s * cout + co0 + wm * 32 + i * 16 + (lane / 16) * 4 + r] = accb[i][r];
+                out[(long long)cout * K + co0 + wm * 32 + i * 16 + (lane / 16) * 4 + r] = accb[i][r];
 }
 
 // Fixed-order sum of the split partials into the FP32 gradient.
@@ -1159,12 +1160,12 @@ hipError_t conv_wgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, co
     const int BN = 4096 / BM;
     if (ly.cout % BM || ly.cin % 8 || dys % 8 || xs % 8) return hipErrorInvalidValue;
     const long long wsz = (long long)ly.cout * K;
+    if (ly.b_off != ly.w_off + wsz) return hipErrorInvalidValue;
     const long long tiles = (long long)(ly.cout / BM) * ((K + BN - 1) / BN);
     // splits: enough workgroups to fill the chip, at least 256 pixels each, within the partial buffer
     long long nsplit = std::max<long long>(1, std::min<long long>(P / 256, (2048 + tiles - 1) / tiles));
     nsplit = std::min<long long>(nsplit, 256);
-    while ((size_t)nsplit * wsz > u->split_floats && nsplit > 1) --nsplit;
-    while ((size_t)nsplit * ly.cout > u->small_floats && nsplit > 1) --nsplit;
+    while ((size_t)nsplit * (wsz + ly.cout) > u->split_floats && nsplit > 1) --nsplit;
     // deeper steps (KP pixels per barrier pair) while every split still holds two of them
     const int KP = wgrad_kp(P, nsplit, H, W);
     long long split_len = (P + nsplit - 1) / nsplit;
@@ -1173,20 +1174,19 @@ hipError_t conv_wgrad(nn_unet* u, const Layer& ly, const __bf16* dY, int dys, co
     const dim3 grid((unsigned)(tiles * nsplit));
     if (KP == 128 && BM == 64)
         hipLaunchKernelGGL((k_conv_wgrad_deep<64, 128>), grid, dim3(256), 0, u->stream, dY, ly.cout, dys, X, ly.cin, xs,
-                           ly.taps, H, W, P, (int)split_len, (int)nsplit, u->split, u->small);
+                           ly.taps, H, W, P, (int)split_len, (int)nsplit, u->split);
     else if (KP == 128)
         hipLaunchKernelGGL((k_conv_wgrad_deep<32, 128>), grid, dim3(256), 0, u->stream, dY, ly.cout, dys, X, ly.cin, xs,
-                           ly.taps, H, W, P, (int)split_len, (int)nsplit, u->split, u->small);
+                           ly.taps, H, W, P, (int)split_len, (int)nsplit, u->split);
     else if (BM == 64)
         hipLaunchKernelGGL(k_conv_wgrad_lds<64>, grid, dim3(256), 0, u->stream, dY, ly.cout, dys, X, ly.cin, xs, ly.taps,
-                           H, W, P, (int)split_len, (int)nsplit, u->split, u->small);
+                           H, W, P, (int)split_len, (int)nsplit, u->split);
     else
         hipLaunchKernelGGL(k_conv_wgrad_lds<32>, grid, dim3(256), 0, u->stream, dY, ly.cout, dys, X, ly.cin, xs, ly.taps,
-                           H, W, P, (int)split_len, (int)nsplit, u->split, u->small);
-    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(wsz)), dim3(256), 0, u->stream, (const float*)u->split, (int)nsplit, wsz,
-                       u->grad + ly.w_off);
-    hipLaunchKernelGGL(k_colsum, dim3(ly.cout), dim3(256), 0, u->stream, (const float*)u->small, (int)nsplit,
-                       ly.cout, u->grad + ly.b_off);
+                           H, W, P, (int)split_len, (int)nsplit, u->split);
+    // weights and biases are adjacent in the parameter vector, as in each split row
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(wsz + ly.cout)), dim3(256), 0, u->stream, (const float*)u->split,
+                       (int)nsplit, wsz + ly.cout, u->grad + ly.w_off);
     return hipGetLastError();
 }
 
