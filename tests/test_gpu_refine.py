@@ -9,7 +9,8 @@ sizes beyond the oracle's reach, a refined cylinder (2D) and sphere (3D) run to 
 the drag and velocity field of the uniform grid of the fine spacing, not those of the coarse one.
 Nested levels (lbm_refine_nest): three levels in 2D and 3D match the oracle's nest step by step,
 the nesting requirements are enforced, and a three-level cylinder gives the drag of the uniform
-grid of the finest spacing.
+grid of the finest spacing. At the size bench.py times, the band refill and the restriction are
+checked against the oracle's transfer functions on the exported states.
 """
 import numpy as np
 import pytest
@@ -353,3 +354,52 @@ def test_three_level_cylinder_drag_matches_the_uniform_finest_grid(lbmib):
     assert abs(cd_n - cd_f) < 1e-2 * cd_f
     assert abs(cd_n - cd_f) < 0.2 * abs(cd_c - cd_f)
     assert du_n < 0.05 and du_n < 0.25 * du_c
+
+
+def test_transfers_at_the_benchmark_size(lbmib):
+    # The refined sphere that bench.py --workload refine times (FP32, coarse 192 x 96 x 96, fine
+    # block 128 x 96 x 96 at (40, 24, 24), band 2), three coupled steps from a perturbed state.
+    # Every band node then holds the second refill: the oracle's interpolation and rescaling of
+    # the coarse state after the step (the restriction leaves the band's coarse sources alone), and
+    # every restricted coarse node the oracle's rescaling of its fine node. Both are checked on the
+    # exported states: the band on 8^3 fine nodes at the block's corners, edges and faces, the
+    # restriction everywhere, within the FP32 rounding of the stored results.
+    coarse, fine, org = wl.refined_sphere(nx=192, ny=96, nz=96, origin=(40, 24, 24), block=(64, 48, 48), diameter=8.0,
+                                          mach=0.2, reynolds=100.0)
+    lat = for_dim(3)
+    prm_c = oracle_params(coarse)
+    prm_f = orf.fine_params(prm_c)
+    print('[refine] benchmark size: transfers against the oracle', flush=True)
+    sc, sf, ref = _solvers(lbmib, coarse, fine, org, 32)
+    sc.set_fields(*wl.random_state_perturbation(coarse, 5))
+    ref.prolong()
+    ref.step(3)
+    fc, ec, H2c = sc.get_state()
+    ff, ef, H2f = sf.get_state()
+    nf = fine.dims
+    scale = np.abs(ff).max()
+    # band
+    worst = 0.0
+    starts = [(0, 0, 0), (120, 88, 88), (0, 88, 40), (60, 0, 0), (0, 44, 60), (120, 40, 0), (56, 88, 88), (64, 40, 88)]
+    for x0, y0, z0 in starts:
+        sub = orf.Block(origin=(org[0] + x0 // 2, org[1] + y0 // 2, org[2] + z0 // 2), size=(4, 4, 4), G=2, R=8)
+        f_o, e_o, H2d = orf.prolong(lat, prm_c, prm_f, fc, ec, H2c, sub)
+        z, y, x = np.meshgrid(np.arange(z0, z0 + 8), np.arange(y0, y0 + 8), np.arange(x0, x0 + 8), indexing='ij')
+        band = ((x < 2) | (x >= nf[0] - 2) | (y < 2) | (y >= nf[1] - 2) | (z < 2) | (z >= nf[2] - 2))
+        assert band.any()
+        g = ff[:, z0:z0 + 8, y0:y0 + 8, x0:x0 + 8]
+        worst = max(worst, np.abs(g[:, band] - f_o[:, band]).max() / scale)
+        assert np.abs(ef[z0:z0 + 8, y0:y0 + 8, x0:x0 + 8][band] - e_o[band]).max() < 1e-6 * np.abs(ef).max()
+        for a in range(3):
+            assert np.abs(H2f[a, a, z0:z0 + 8, y0:y0 + 8, x0:x0 + 8][band] - H2d[a][band]).max() < 1e-9
+    # restriction
+    blk = orf.Block(origin=org, size=tuple(n // 2 for n in nf), G=2, R=8)
+    st_c = olbm.State(f=fc.copy(), rhoE=ec.copy(), H1=np.zeros_like(ec), H2=H2c.copy())
+    st_f = olbm.State(f=ff, rhoE=ef, H1=np.zeros_like(ef), H2=H2f)
+    new_c = orf.restrict(lat, prm_c, prm_f, st_c, st_f, blk)
+    fi, ci = orf.restriction_nodes(blk)
+    sel = (slice(None),) + np.ix_(*reversed(ci))
+    rworst = np.abs(new_c.f[sel] - fc[sel]).max() / scale
+    print(f'[refine] band vs oracle {worst:.2e}, restriction vs oracle {rworst:.2e} (of max |f|)', flush=True)
+    assert worst < 1e-6 and rworst < 1e-6
+    assert np.abs(new_c.rhoE - ec).max() < 1e-6 * np.abs(ec).max()
