@@ -127,8 +127,10 @@ int ib_set_markers(lbm_handle* h, int m, const double* X, const double* normal,
 /* Enqueue n time steps on the handle's stream (Sec. 2.5). Asynchronous; the last step also
  * accumulates the FP64 velocity residual r = ||u^{n+1} - u^n|| / (|u_inf| sqrt(N)) over the
  * stored states and a non-finite check (read with lbm_residual): inside the fused sweep, or by a
- * separate pass for the three-pass sweep and the characteristic outlet. Errors: LBM_E_INVAL
- * (n < 0), LBM_E_HIP. */
+ * separate pass for the three-pass sweep and the characteristic outlet. Calls of 5 or more steps
+ * replay pairs of steps as a HIP graph, captured on the first such call and again after
+ * ib_set_markers (results equal to stepping one at a time). Errors: LBM_E_INVAL (n < 0),
+ * LBM_E_HIP. */
 int lbm_step(lbm_handle* h, int n);
 
 /* As lbm_step, and also times the launches of every step with HIP events recorded on the

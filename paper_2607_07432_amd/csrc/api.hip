@@ -146,25 +146,6 @@ int fail(lbm_handle* h, int code, const std::string& msg) {
         if (e_ != hipSuccess) return fail((h), LBM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-template <class S>
-StateP<S> current(lbm_handle* h) {
-    return h->cur == 0 ? stateA<S>(h) : stateB<S>(h);
-}
-template <class S>
-StateP<S> other(lbm_handle* h) {
-    return h->cur == 0 ? stateB<S>(h) : stateA<S>(h);
-}
-
-// Dispatch a functor on (lattice, storage type).
-template <class F>
-hipError_t dispatch(lbm_handle* h, F&& f) {
-    if (h->D == 2) {
-        if (h->p.precision == LBM_F64) return f(D2Q9{}, double{});
-        return f(D2Q9{}, float{});
-    }
-    if (h->p.precision == LBM_F64) return f(D3Q19{}, double{});
-    return f(D3Q19{}, float{});
-}
 
 void refresh_args(lbm_handle* h) {
     h->args.rows.nrows = (int)h->geom.rows.size();
@@ -484,12 +465,64 @@ int run_steps(lbm_handle* h, int n, hipEvent_t* ev, bool want_resid = true) {
     return LBM_OK;
 }
 
+// Calls of at least this many steps replay the two-step graph.
+constexpr int kGraphMinSteps = 5;
+
+// Capture (once per state index and body) the two steps from the current state. Nothing runs
+// during the capture, and the state index ends where it started.
+int ensure_graph(lbm_handle* h) {
+    if (h->graph_exec && h->graph_cur == h->cur && h->graph_geom == h->geom_version) return LBM_OK;
+    if (h->graph_exec) {
+        hipGraphExecDestroy(h->graph_exec);
+        h->graph_exec = nullptr;
+    }
+    if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    const int cur0 = h->cur, stepped = h->stepped, any = h->any_step;
+    hipStream_t user = h->stream;
+    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(h, LBM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    h->stream = h->cap_stream;
+    const int rc = run_steps(h, 2, nullptr, false);
+    h->stream = user;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->cap_stream, &g);
+    h->stepped = stepped;
+    h->any_step = any;
+    if (h->cur != cur0) {   // a failed capture may stop after one step
+        h->cur = cur0;
+        refresh_args(h);
+    }
+    if (rc != LBM_OK || e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return rc != LBM_OK ? rc : fail(h, LBM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->graph_exec = nullptr;
+        return fail(h, LBM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    h->graph_cur = h->cur;
+    h->graph_geom = h->geom_version;
+    return LBM_OK;
+}
+
 }  // namespace
 
 int lbm_step(lbm_handle* h, int n) {
     if (!h) return LBM_E_INVAL;
     if (n < 0) return fail(h, LBM_E_INVAL, "n < 0");
-    return run_steps(h, n, nullptr);
+    if (n < kGraphMinSteps) return run_steps(h, n, nullptr);
+    // pairs of steps replay the captured graph; an odd step and the last one (which forms the
+    // residual) run directly
+    int m = n - 1;
+    if (m % 2) {
+        if (int rc = run_steps(h, 1, nullptr, false)) return rc;
+        --m;
+    }
+    if (int rc = ensure_graph(h)) return rc;
+    for (int i = 0; i < m / 2; ++i) HIPCHK(h, hipGraphLaunch(h->graph_exec, h->stream));
+    return run_steps(h, 1, nullptr, true);
 }
 
 int lbm_step_timed(lbm_handle* h, int n, double* kernel_ms) {
@@ -749,7 +782,12 @@ int ib_marker_state(lbm_handle* h, double* F, double* Wib, double* Qib, double* 
     return LBM_OK;
 }
 
-void lbm_destroy(lbm_handle* h) { delete h; }
+void lbm_destroy(lbm_handle* h) {
+    if (!h) return;
+    if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    delete h;
+}
 
 namespace {
 

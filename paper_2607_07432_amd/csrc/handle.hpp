@@ -55,6 +55,11 @@ struct lbm_handle {
     // (y unused in 2D, where the marching axis is y); empty when min > max. Fused-sweep tiles whose
     // footprint misses it run without the forcing path.
     int fbox[6] = {1, 0, 1, 0, 1, 0};
+    // Two steps without the residual, captured as a HIP graph from state index graph_cur for body
+    // version graph_geom on a private stream, replayed on `stream` by long lbm_step calls.
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int graph_cur = -1, graph_geom = -1;
     std::string err;
 };
 
@@ -67,6 +72,27 @@ StateP<S> stateA(lbm_handle* h) {
 template <class S>
 StateP<S> stateB(lbm_handle* h) {
     return {(S*)h->d.fB, (S*)h->d.eB, (S*)h->d.hB};
+}
+
+// The current state (the last step's output) and the other one (its input).
+template <class S>
+StateP<S> current(lbm_handle* h) {
+    return h->cur == 0 ? stateA<S>(h) : stateB<S>(h);
+}
+template <class S>
+StateP<S> other(lbm_handle* h) {
+    return h->cur == 0 ? stateB<S>(h) : stateA<S>(h);
+}
+
+// Call f(lattice tag, storage type tag) for the handle's lattice and precision.
+template <class F>
+hipError_t dispatch(lbm_handle* h, F&& f) {
+    if (h->D == 2) {
+        if (h->p.precision == LBM_F64) return f(D2Q9{}, double{});
+        return f(D2Q9{}, float{});
+    }
+    if (h->p.precision == LBM_F64) return f(D3Q19{}, double{});
+    return f(D3Q19{}, float{});
 }
 
 // Recompute the kernel argument blocks of a handle from its current state index and body.

@@ -219,24 +219,6 @@ __global__ void __launch_bounds__(RTPB) k_refine_restrict(RefineGeom g, RefineGa
 
 unsigned blocks_of(long long n) { return (unsigned)((n + RTPB - 1) / RTPB); }
 
-template <class S>
-StateP<S> cur_of(lbm_handle* h) {
-    return h->cur == 0 ? stateA<S>(h) : stateB<S>(h);
-}
-template <class S>
-StateP<S> prev_of(lbm_handle* h) {
-    return h->cur == 0 ? stateB<S>(h) : stateA<S>(h);
-}
-
-template <class F>
-hipError_t dispatch2(lbm_handle* h, F&& f) {
-    if (h->D == 2) {
-        if (h->p.precision == LBM_F64) return f(D2Q9{}, double{});
-        return f(D2Q9{}, float{});
-    }
-    if (h->p.precision == LBM_F64) return f(D3Q19{}, double{});
-    return f(D3Q19{}, float{});
-}
 
 thread_local std::string g_refine_error;
 
@@ -308,26 +290,26 @@ int coupled_step(lbm_refine* r) {
             return rfail(r, rc, std::string("fine step: ") + f->err);
         }
         // coarse: the previous state is the one before this coupled step, the current one after it
-        hipError_t e = dispatch2(c, [&](auto L, auto S) {
+        hipError_t e = dispatch(c, [&](auto L, auto S) {
             using LT = decltype(L);
             using ST = decltype(S);
             // at k = 2 the band takes the coarse state after the step alone
             if (r->g.nband > 0 && k == 1)
                 hipLaunchKernelGGL((k_refine_prolong<LT, ST, false, true>), dim3(blocks_of(r->g.nband)), dim3(RTPB), 0,
-                                   c->stream, r->g, r->q, prev_of<ST>(c), cur_of<ST>(c), 0.5, cur_of<ST>(f));
+                                   c->stream, r->g, r->q, other<ST>(c), current<ST>(c), 0.5, current<ST>(f));
             else if (r->g.nband > 0)
                 hipLaunchKernelGGL((k_refine_prolong<LT, ST, false, false>), dim3(blocks_of(r->g.nband)), dim3(RTPB),
-                                   0, c->stream, r->g, r->q, prev_of<ST>(c), cur_of<ST>(c), 1.0, cur_of<ST>(f));
+                                   0, c->stream, r->g, r->q, other<ST>(c), current<ST>(c), 1.0, current<ST>(f));
             return hipGetLastError();
         });
         if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine band: ") + hipGetErrorString(e));
     }
-    hipError_t e = dispatch2(c, [&](auto L, auto S) {
+    hipError_t e = dispatch(c, [&](auto L, auto S) {
         using LT = decltype(L);
         using ST = decltype(S);
         if (r->g.nrest > 0)
             hipLaunchKernelGGL((k_refine_restrict<LT, ST>), dim3(blocks_of(r->g.nrest)), dim3(RTPB), 0, c->stream,
-                               r->g, r->q, cur_of<ST>(f), cur_of<ST>(c));
+                               r->g, r->q, current<ST>(f), current<ST>(c));
         return hipGetLastError();
     });
     if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine restrict: ") + hipGetErrorString(e));
@@ -406,11 +388,11 @@ int lbm_refine_create(lbm_handle* coarse, lbm_handle* fine, const int* origin, i
 int lbm_refine_prolong(lbm_refine* r) {
     if (!r) return LBM_E_INVAL;
     lbm_handle *c = r->coarse, *f = r->fine;
-    hipError_t e = dispatch2(c, [&](auto L, auto S) {
+    hipError_t e = dispatch(c, [&](auto L, auto S) {
         using LT = decltype(L);
         using ST = decltype(S);
         hipLaunchKernelGGL((k_refine_prolong<LT, ST, true, false>), dim3(blocks_of(r->g.Nf)), dim3(RTPB), 0,
-                           c->stream, r->g, r->q, cur_of<ST>(c), cur_of<ST>(c), 1.0, cur_of<ST>(f));
+                           c->stream, r->g, r->q, current<ST>(c), current<ST>(c), 1.0, current<ST>(f));
         return hipGetLastError();
     });
     if (e == hipSuccess && !f->geom.rows.empty()) {
