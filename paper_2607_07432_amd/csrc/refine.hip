@@ -87,24 +87,26 @@ __device__ __forceinline__ void node_of(const RefineGeom& g, long long k, int* x
 
 // Values of coarse column ix combined over the y (and z) corners of a fine node: for the Q
 // populations f~, e and the D - 1 stored history components, sum over corners of w_yz times the
-// state (1 - wt) A + wt B (B alone unless TWO).
+// state (1 - wt) A + wt B (B alone unless TWO). The sums are taken in the storage type (the
+// weights 1/2 and 1/4 are exact; FP32 storage keeps the register footprint, and so the number of
+// load round trips, half that of FP64 sums).
 template <class L, class S, bool TWO>
-__device__ __forceinline__ void gather_yz(const RefineGeom& g, const StateP<S>& A, const StateP<S>& B, double wt,
-                                          int ix, const int* i0, const double* fr, double* Y) {
+__device__ __forceinline__ void gather_yz(const RefineGeom& g, const StateP<S>& A, const StateP<S>& B, S wt, int ix,
+                                          const int* i0, const S* fr, S* Y) {
     constexpr int D = L::D, Q = L::Q, NV = Q + D;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Y[v] = 0.0;
-    const double wa = 1.0 - wt;
+    for (int v = 0; v < NV; ++v) Y[v] = S(0);
+    const S wa = S(1) - wt;
 #pragma unroll
     for (int cb = 0; cb < (1 << (D - 1)); ++cb) {
         const int by = cb & 1, bz = (cb >> 1) & 1;
-        double w = by ? fr[1] : 1.0 - fr[1];
-        if (D == 3) w *= bz ? fr[2] : 1.0 - fr[2];
-        if (w == 0.0) continue;   // the same for every node of a row
+        S w = by ? fr[1] : S(1) - fr[1];
+        if (D == 3) w *= bz ? fr[2] : S(1) - fr[2];
+        if (w == S(0)) continue;   // the same for every node of a row
         const long long n = ix + (long long)g.nc[0] * ((i0[1] + by) + (long long)g.nc[1] * (i0[2] + bz));
         auto at = [&](const S* a, const S* b, long long off) {
-            const double vb = double(b[off]);
-            return TWO ? wa * double(a[off]) + wt * vb : vb;
+            const S vb = b[off];
+            return TWO ? wa * a[off] + wt * vb : vb;
         };
 #pragma unroll
         for (int i = 0; i < Q; ++i) Y[i] += w * at(A.f, B.f, (long long)i * g.Nc + n);
@@ -132,22 +134,25 @@ __global__ void __launch_bounds__(RTPB) k_refine_prolong(RefineGeom g, RefineGas
     node_of<D, ALL>(g, k + 1 < total ? k + 1 : k, xn);
     const bool next_ok = (threadIdx.x & 63) != 63 && xn[0] == x[0] + 1 && xn[1] == x[1] && xn[2] == x[2];
     int i0[3];
-    double fr[3];
+    S fr[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         i0[a] = a < D ? g.org[a] + (x[a] >> 1) : 0;
-        fr[a] = a < D ? 0.5 * (x[a] & 1) : 0.0;
+        fr[a] = a < D ? S(0.5) * S(x[a] & 1) : S(0);
     }
-    double Y[NV], Yn[NV];
-    gather_yz<L, S, TWO>(g, A, B, wt, i0[0], i0, fr, Y);
+    S Ys[NV], Yn[NV];
+    gather_yz<L, S, TWO>(g, A, B, S(wt), i0[0], i0, fr, Ys);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Yn[v] = __shfl_down(Y[v], 1, 64);
+    for (int v = 0; v < NV; ++v) Yn[v] = __shfl_down(Ys[v], 1, 64);
     if (x[0] & 1) {
-        if (!next_ok) gather_yz<L, S, TWO>(g, A, B, wt, i0[0] + 1, i0, fr, Yn);
+        if (!next_ok) gather_yz<L, S, TWO>(g, A, B, S(wt), i0[0] + 1, i0, fr, Yn);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Y[v] = 0.5 * Y[v] + 0.5 * Yn[v];
+        for (int v = 0; v < NV; ++v) Ys[v] = S(0.5) * Ys[v] + S(0.5) * Yn[v];
     }
     if (!active) return;
+    double Y[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Y[v] = double(Ys[v]);
     double rho = 1.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
