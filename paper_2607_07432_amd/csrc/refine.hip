@@ -11,6 +11,7 @@
 #include <cmath>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "handle.hpp"
 
@@ -240,6 +241,12 @@ struct lbm_refine {
     int margin = 0;
     lbm_refine* child = nullptr;    // coupling of the fine handle with a finer block, or NULL
     lbm_refine* parent = nullptr;   // coupling whose fine handle is this one's coarse handle
+    // Two coupled steps (every level returns to its state index) captured as a HIP graph on a
+    // private stream, for the key below: coarse state index, then per level its handle, state
+    // index and body version (an outermost coupling only).
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::vector<long long> graph_key;
     std::string err;
 };
 
@@ -320,6 +327,77 @@ int coupled_step(lbm_refine* r) {
     if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine restrict: ") + hipGetErrorString(e));
     return LBM_OK;
 }
+
+// Every handle of the nest, coarsest first.
+std::vector<lbm_handle*> nest_handles(lbm_refine* r) {
+    std::vector<lbm_handle*> hs{r->coarse};
+    for (lbm_refine* p = r; p; p = p->child) hs.push_back(p->fine);
+    return hs;
+}
+
+std::vector<long long> nest_key(lbm_refine* r) {
+    std::vector<long long> k;
+    for (lbm_handle* h : nest_handles(r)) {
+        k.push_back(reinterpret_cast<long long>(h));
+        k.push_back(h->cur);
+        k.push_back(h->geom_version);
+    }
+    return k;
+}
+
+// Capture (once per key) two coupled steps from the current states. Nothing runs during the
+// capture, and every level's state index ends where it started.
+int ensure_nest_graph(lbm_refine* r) {
+    const std::vector<long long> key = nest_key(r);
+    if (r->graph_exec && r->graph_key == key) return LBM_OK;
+    if (r->graph_exec) {
+        hipGraphExecDestroy(r->graph_exec);
+        r->graph_exec = nullptr;
+    }
+    if (!r->cap_stream) {
+        const hipError_t e = hipStreamCreateWithFlags(&r->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("graph stream: ") + hipGetErrorString(e));
+    }
+    const std::vector<lbm_handle*> hs = nest_handles(r);
+    std::vector<int> cur0, stepped, any;
+    for (lbm_handle* h : hs) {
+        cur0.push_back(h->cur);
+        stepped.push_back(h->stepped);
+        any.push_back(h->any_step);
+    }
+    hipStream_t user = r->coarse->stream;
+    hipError_t e = hipStreamBeginCapture(r->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    for (lbm_handle* h : hs) h->stream = r->cap_stream;
+    int rc = coupled_step(r);
+    if (rc == LBM_OK) rc = coupled_step(r);
+    for (lbm_handle* h : hs) h->stream = user;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(r->cap_stream, &g);
+    for (size_t i = 0; i < hs.size(); ++i) {
+        hs[i]->stepped = stepped[i];
+        hs[i]->any_step = any[i];
+        if (hs[i]->cur != cur0[i]) {   // a failed capture may stop part way
+            hs[i]->cur = cur0[i];
+            refresh_handle_args(hs[i]);
+        }
+    }
+    if (rc != LBM_OK || e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return rc != LBM_OK ? rc : rfail(r, LBM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&r->graph_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        r->graph_exec = nullptr;
+        return rfail(r, LBM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    r->graph_key = key;
+    return LBM_OK;
+}
+
+// Calls of at least this many coupled steps replay the two-step graph.
+constexpr int kNestGraphMinSteps = 3;
 
 }  // namespace
 
@@ -414,12 +492,26 @@ int lbm_refine_step(lbm_refine* r, int n) {
     if (n < 0) return rfail(r, LBM_E_INVAL, "n < 0");
     if (r->parent) return rfail(r, LBM_E_INVAL, "a nested coupling is stepped through its outer coupling");
     if (int rc = check_bodies(r)) return rc;
-    for (int s = 0; s < n; ++s) {
-        if (int rc = coupled_step(r)) return rc;
-        if (s == n - 1)
-            if (int rc = residual_handle(r->coarse))
-                return rfail(r, rc, std::string("coarse residual: ") + r->coarse->err);
+    if (n == 0) return LBM_OK;
+    int m = n - 1;                  // coupled steps before the last one
+    if (n >= kNestGraphMinSteps) {
+        // pairs replay the captured graph; an odd step and the last one run directly
+        if (m % 2) {
+            if (int rc = coupled_step(r)) return rc;
+            --m;
+        }
+        if (int rc = ensure_nest_graph(r)) return rc;
+        for (int i = 0; i < m / 2; ++i) {
+            const hipError_t e = hipGraphLaunch(r->graph_exec, r->coarse->stream);
+            if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("graph launch: ") + hipGetErrorString(e));
+        }
+        for (lbm_handle* h : nest_handles(r)) h->stepped = h->any_step = 1;
+    } else {
+        for (int s = 0; s < m; ++s)
+            if (int rc = coupled_step(r)) return rc;
     }
+    if (int rc = coupled_step(r)) return rc;
+    if (int rc = residual_handle(r->coarse)) return rfail(r, rc, std::string("coarse residual: ") + r->coarse->err);
     return LBM_OK;
 }
 
@@ -444,8 +536,16 @@ int lbm_refine_nest(lbm_refine* outer, lbm_refine* inner) {
 
 void lbm_refine_destroy(lbm_refine* r) {
     if (!r) return;
-    if (r->parent) r->parent->child = nullptr;
+    if (r->parent) {
+        r->parent->child = nullptr;
+        if (r->parent->graph_exec) {          // its graph stepped this coupling
+            hipGraphExecDestroy(r->parent->graph_exec);
+            r->parent->graph_exec = nullptr;
+        }
+    }
     if (r->child) r->child->parent = nullptr;
+    if (r->graph_exec) hipGraphExecDestroy(r->graph_exec);
+    if (r->cap_stream) hipStreamDestroy(r->cap_stream);
     delete r;
 }
 

@@ -403,3 +403,39 @@ def test_transfers_at_the_benchmark_size(lbmib):
     print(f'[refine] band vs oracle {worst:.2e}, restriction vs oracle {rworst:.2e} (of max |f|)', flush=True)
     assert worst < 1e-6 and rworst < 1e-6
     assert np.abs(new_c.rhoE - ec).max() < 1e-6 * np.abs(ec).max()
+
+
+def _pair(lbmib, cases, origins, precision):
+    s = [lbmib.Solver.from_case(c, precision=precision, markers=c.X is not None) for c in cases]
+    r = [lbmib.Refinement(s[k], s[k + 1], origins[k]) for k in range(len(origins))]
+    for k in range(len(r) - 1):
+        r[k].nest(r[k + 1])
+    return s, r
+
+
+@pytest.mark.parametrize('levels,precision', [(2, 64), (2, 32), (3, 32)])
+def test_graph_replay_of_coupled_steps_equals_single_steps(lbmib, levels, precision):
+    # lbm_refine_step replays pairs of coupled steps as a captured graph from three steps on; every
+    # replay gives the states of single coupled steps bit for bit, host reads in between
+    if levels == 2:
+        coarse, fine, org = _cases(2, True)
+        cases, origins = [coarse, fine], (org,)
+    else:
+        cases, origins = wl.nested_cylinder()
+    print(f'[refine] graph replay, {levels} levels, f{precision}', flush=True)
+    sa, ra = _pair(lbmib, cases, origins, precision)
+    sb, rb = _pair(lbmib, cases, origins, precision)
+    st = random_state(cases[0], None, seed=9)
+    for s, r in ((sa, ra), (sb, rb)):
+        s[0].set_state(st.f, st.rhoE, st.H2)
+        for x in r:
+            x.prolong()
+    for n in (7, 4, 3, 6):
+        ra[0].step(n)
+        for _ in range(n):
+            rb[0].step(1)
+        for a, b in zip(sa, sb):
+            fa, ea, ha = a.get_state()
+            fb, eb, hb = b.get_state()
+            assert np.array_equal(fa, fb) and np.array_equal(ea, eb) and np.array_equal(ha, hb), n
+        assert ra[0].residual() == rb[0].residual()
