@@ -214,7 +214,9 @@ size_t lbm_batch_workspace_bytes(lbm_handle* const* cases, int n);
 /* Create a batch. dev_workspace: caller-owned device memory of at least
  * lbm_batch_workspace_bytes bytes, 256-byte aligned. autotune = 1 times the sweep for each tile
  * width (62, 126, 254 nodes) and chunk length (16, 32, 64, 128 rows) on the current states and
- * keeps the fastest (the states are left unchanged); 0 takes 62 x 32.
+ * keeps the fastest (the states are left unchanged); 0 takes width 62 and chunks of 32 rows, or
+ * of 16 rows when 32-row chunks would give fewer than eight work items per workgroup of the
+ * persistent launch.
  * Errors: LBM_E_INVAL (see requirements), LBM_E_NOMEM, LBM_E_HIP. */
 int lbm_batch_create(lbm_handle* const* cases, int n, void* dev_workspace, size_t bytes, int autotune,
                      lbm_batch** out);

@@ -331,6 +331,16 @@ int rebuild(lbm_batch* b, int tx, int chunk) {
     return LBM_OK;
 }
 
+// Chunk length of an untuned batch at tile width 62: 32 rows, or 16 where 32-row chunks would
+// leave fewer than eight work items per workgroup of the persistent grid (a small batch, such as
+// the tail of cases still marching to steady state), where the shorter items balance better.
+template <class S>
+int untuned_chunk(lbm_batch* b) {
+    fill_desc<S>(b, 62, 32);
+    const long long slots = persistent_grid<S>(62, 1 << 30);
+    return b->total_items >= 8 * slots ? 32 : 16;
+}
+
 template <class S>
 int in_sync(lbm_batch* b) {
     for (size_t c = 0; c < b->hs.size(); ++c) {
@@ -438,7 +448,7 @@ int lbm_batch_create(lbm_handle* const* cases, int n, void* ws, size_t bytes, in
     }
     int rc = by_precision(b, [&](auto S) {
         using ST = decltype(S);
-        return tune ? autotune<ST>(b) : rebuild<ST>(b, 62, 32);
+        return tune ? autotune<ST>(b) : rebuild<ST>(b, 62, untuned_chunk<ST>(b));
     });
     if (rc != LBM_OK) {
         g_batch_error = b->err;

@@ -199,3 +199,21 @@ def test_batch_refuses_invalid(lbmib):
     with pytest.raises(lbmib.LbmError):
         b.set_tile(62, 0)
     b.close()
+
+
+def test_untuned_small_batch_takes_short_chunks(lbmib):
+    """Without autotuning a batch too small to give eight 32-row items per workgroup of the
+    persistent launch takes 16-row chunks; its steps equal the single-grid steps (FP64)."""
+    cases = small_cases(3, seed0=3100)
+    ref = solvers_for(lbmib, cases, lbmib.F64)
+    bat = solvers_for(lbmib, cases, lbmib.F64)
+    for s in ref:
+        s.step(5)
+    batch = lbmib.Batch(bat, autotune=False)
+    cfg = batch.config()
+    print('untuned', cfg, flush=True)
+    assert cfg['tile_x'] == 62 and cfg['chunk'] == 16
+    batch.step(5)
+    for a, b in zip(ref, bat):
+        assert state_rel(b.get_state(), a.get_state()) <= 1e-12
+    batch.close()
