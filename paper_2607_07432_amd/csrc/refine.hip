@@ -39,6 +39,16 @@ struct RefineGas {
 
 __device__ __forceinline__ double taubar_of(double mu, double rho) { return mu * 3.0 / rho + 0.5; }
 
+// Workgroups are dispatched to the eight XCDs in turn (workgroup w on XCD w % 8). Logical block
+// (w % 8) * per + w / 8 gives each XCD a contiguous range of items, so that the workgroups reading
+// the same coarse (or fine) lines share one L2; -1 for the padding workgroups of the last range.
+__device__ __forceinline__ long long xcd_block(long long nblocks) {
+    const long long per = (nblocks + 7) / 8;
+    const long long w = blockIdx.x;
+    const long long lb = (w % 8) * per + w / 8;
+    return lb < nblocks ? lb : -1;
+}
+
 // Fine coordinates of band node k: in 3D the z slabs first, then, plane by plane, the y rows and the
 // x columns of the ring of one plane.
 template <int D>
@@ -127,7 +137,9 @@ __global__ void __launch_bounds__(RTPB) k_refine_prolong(RefineGeom g, RefineGas
                                                          double wt, StateP<S> F) {
     constexpr int D = L::D, Q = L::Q, NV = Q + D;
     const long long total = ALL ? g.Nf : g.nband;
-    const long long kk = (long long)blockIdx.x * RTPB + threadIdx.x;
+    const long long lb = xcd_block((total + RTPB - 1) / RTPB);
+    if (lb < 0) return;
+    const long long kk = lb * RTPB + threadIdx.x;
     const bool active = kk < total;
     const long long k = active ? kk : total - 1;   // idle lanes still take part in the shuffle
     int x[3] = {0, 0, 0}, xn[3] = {0, 0, 0};
@@ -185,7 +197,9 @@ __global__ void __launch_bounds__(RTPB) k_refine_prolong(RefineGeom g, RefineGas
 template <class L, class S>
 __global__ void __launch_bounds__(RTPB) k_refine_restrict(RefineGeom g, RefineGas q, StateP<S> F, StateP<S> C) {
     constexpr int D = L::D, Q = L::Q;
-    const long long k = (long long)blockIdx.x * RTPB + threadIdx.x;
+    const long long lb = xcd_block((g.nrest + RTPB - 1) / RTPB);
+    if (lb < 0) return;
+    const long long k = lb * RTPB + threadIdx.x;
     if (k >= g.nrest) return;
     int xf[3] = {0, 0, 0};
     xf[0] = g.rlo[0] + 2 * (int)(k % g.rn[0]);
@@ -223,7 +237,8 @@ __global__ void __launch_bounds__(RTPB) k_refine_restrict(RefineGeom g, RefineGa
     for (int c = 0; c < D - 1; ++c) C.h2[(long long)c * g.Nc + nc] = S(2.0 * double(F.h2[(long long)c * g.Nf + nf]));
 }
 
-unsigned blocks_of(long long n) { return (unsigned)((n + RTPB - 1) / RTPB); }
+// Workgroups for n items: whole blocks, rounded up to a multiple of the eight XCDs (see xcd_block).
+unsigned blocks_of(long long n) { return (unsigned)(((n + RTPB - 1) / RTPB + 7) / 8 * 8); }
 
 
 thread_local std::string g_refine_error;
