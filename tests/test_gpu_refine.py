@@ -439,3 +439,16 @@ def test_graph_replay_of_coupled_steps_equals_single_steps(lbmib, levels, precis
             fb, eb, hb = b.get_state()
             assert np.array_equal(fa, fb) and np.array_equal(ea, eb) and np.array_equal(ha, hb), n
         assert ra[0].residual() == rb[0].residual()
+    # a new body on the finest level is captured anew
+    fin = cases[-1]
+    X = fin.X + np.array([0.37, -0.21] + ([0.13] if fin.dim == 3 else []))
+    for s in (sa[-1], sb[-1]):
+        s.set_markers(X, fin.n, fin.u_wall, fin.t_kind, fin.t_value, fin.method)
+    ra[0].step(5)
+    for _ in range(5):
+        rb[0].step(1)
+    for a, b in zip(sa, sb):
+        fa, ea, ha = a.get_state()
+        fb, eb, hb = b.get_state()
+        assert np.array_equal(fa, fb) and np.array_equal(ea, eb) and np.array_equal(ha, hb)
+    assert ra[0].residual() == rb[0].residual()
