@@ -270,6 +270,16 @@ int lbm_init_grid(const lbm_params* p, void* ws, size_t bytes, void* stream, lbm
 
     SweepArgs& a = h->args;
     a.grid = {p->nx, p->ny, p->nz, h->N, p->bc_x};
+    if (h->chunk <= 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) cus = 0;
+        if (D == 2)
+            h->chunk = p->precision == LBM_F64 ? fused_auto_chunk<D2Q9, double>(a.grid, cus)
+                                               : fused_auto_chunk<D2Q9, float>(a.grid, cus);
+        else
+            h->chunk = p->precision == LBM_F64 ? fused_auto_chunk<D3Q19, double>(a.grid, cus)
+                                               : fused_auto_chunk<D3Q19, float>(a.grid, cus);
+    }
     a.gas = {p->mu, p->lambda_, p->gamma, p->sigma, Cv, Cv + 1.0 / 3.0, p->with_aC, 1.0 / Cv};
     for (int i = 0; i < 19; ++i) a.fs.fdev[i] = i < Q ? fd[i] : 0.0;
     double uu = 0;

@@ -46,7 +46,7 @@ struct lbm_handle {
     lbmib::Geometry geom;
     std::vector<double> host_stage;
     int method = 0;
-    int chunk = 0;         // planes per workgroup of the fused sweep (0: per-lattice default)
+    int chunk = 0;         // planes per work item of the fused sweep (set by lbm_init_grid)
     int markers_set = 0;
     int stepped = 0;       // a step has run since the body was set
     int any_step = 0;

@@ -125,6 +125,11 @@ template <class L, class S>
 hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, const int* fbox,
                              hipStream_t st, double* rpart = nullptr, int rcap = 0, int* rparts = nullptr);
 
+// Planes per work item of the fused sweep on this grid for a device of `cus` compute units:
+// shorter than the lattice's default only where the default leaves part of the chip idle.
+template <class L, class S>
+int fused_auto_chunk(const GridP& g, int cus);
+
 template <class L, class S>
 hipError_t launch_init_state(const SweepArgs& a, StateP<S> A, hipStream_t st);
 template <class L, class S>

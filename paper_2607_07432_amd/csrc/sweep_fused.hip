@@ -765,6 +765,33 @@ hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int c
     return launch_fused_tile<L, S, TL::TX, TL::TY>(a, A, B, chunk, TL::CHUNK, fbox, st, rpart, rcap, rparts);
 }
 
+// Planes per work item for a grid: the lattice's default (the best measured on grids that fill the
+// chip several times over), or, where that leaves fewer work items than the chip holds at once
+// (slots workgroups), the shortest of 32, 24, 16, 12, 8 planes that still fits in one round of
+// slots; a chunk's first planes recompute what the previous chunk's last ones computed, so the
+// states do not depend on the choice.
+template <class L, class S>
+int fused_auto_chunk(const GridP& g, int cus) {
+    using TL = Tile<L, S>;
+    constexpr int threads = (TL::TX + 2) * (L::D == 3 ? TL::TY + 2 : 1);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fused<L, S, S, TL::TX, TL::TY, 0, false>, threads, 0) !=
+            hipSuccess ||
+        occ < 1)
+        occ = 1;
+    const long long slots = (long long)occ * (cus > 0 ? cus : 256);
+    const long long tiles = (long long)((g.nx + TL::TX - 1) / TL::TX) * (L::D == 3 ? (g.ny + TL::TY - 1) / TL::TY : 1);
+    const int nm = L::D == 3 ? g.nz : g.ny;
+    auto items = [&](int c) { return tiles * ((nm + c - 1) / c); };
+    int chunk = TL::CHUNK;
+    for (int c : {32, 24, 16, 12, 8}) {
+        if (c >= chunk || items(chunk) >= slots) continue;
+        if (items(c) > slots) break;
+        chunk = c;
+    }
+    return chunk;
+}
+
 template <class L, class S>
 hipError_t launch_fused_batch(const CaseDesc<S>* cases, int ncases, int total_items, int tx, int grid, int g,
                               hipStream_t st) {
@@ -800,6 +827,10 @@ template hipError_t launch_fused_batch<D2Q9, float>(const CaseDesc<float>*, int,
 template hipError_t launch_fused_batch<D2Q9, double>(const CaseDesc<double>*, int, int, int, int, int, hipStream_t);
 template int fused_batch_occupancy<D2Q9, float>(int);
 template int fused_batch_occupancy<D2Q9, double>(int);
+template int fused_auto_chunk<D2Q9, float>(const GridP&, int);
+template int fused_auto_chunk<D2Q9, double>(const GridP&, int);
+template int fused_auto_chunk<D3Q19, float>(const GridP&, int);
+template int fused_auto_chunk<D3Q19, double>(const GridP&, int);
 
 template hipError_t launch_fused_step<D2Q9, float>(const SweepArgs&, StateP<float>, StateP<float>, int, const int*, hipStream_t,
                                                   double*, int, int*);
