@@ -125,8 +125,8 @@ template <class L, class S>
 hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int chunk, const int* fbox,
                              hipStream_t st, double* rpart = nullptr, int rcap = 0, int* rparts = nullptr);
 
-// Planes per work item of the fused sweep on this grid for a device of `cus` compute units:
-// shorter than the lattice's default only where the default leaves part of the chip idle.
+// Planes per work item of the fused sweep on this grid for a device of `cus` compute units
+// (chosen from the number of work items each length gives against the workgroups the chip holds).
 template <class L, class S>
 int fused_auto_chunk(const GridP& g, int cus);
 

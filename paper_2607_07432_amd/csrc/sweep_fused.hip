@@ -765,11 +765,13 @@ hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int c
     return launch_fused_tile<L, S, TL::TX, TL::TY>(a, A, B, chunk, TL::CHUNK, fbox, st, rpart, rcap, rparts);
 }
 
-// Planes per work item for a grid: the lattice's default (the best measured on grids that fill the
-// chip several times over), or, where that leaves fewer work items than the chip holds at once
-// (slots workgroups), the shortest of 32, 24, 16, 12, 8 planes that still fits in one round of
-// slots; a chunk's first planes recompute what the previous chunk's last ones computed, so the
-// states do not depend on the choice.
+// Planes per work item for a grid on a device with `cus` compute units. A work item costs about
+// its planes plus three (a chunk's first planes recompute what the previous chunk's last ones
+// computed, so the states do not depend on the choice), and the items run in rounds of as many
+// workgroups as the chip holds at once; the chunk minimising rounds x (planes + 3) over 64, 48, 32,
+// 24, 16, 12 and 8 planes is taken, the longer one on a tie. Measured sweep times order the
+// chunks as this estimate does on 384x192x192, 384x192x96, 256x128x128 (FP32) and on 384x192x192
+// and 192x96x96 (FP64).
 template <class L, class S>
 int fused_auto_chunk(const GridP& g, int cus) {
     using TL = Tile<L, S>;
@@ -782,14 +784,18 @@ int fused_auto_chunk(const GridP& g, int cus) {
     const long long slots = (long long)occ * (cus > 0 ? cus : 256);
     const long long tiles = (long long)((g.nx + TL::TX - 1) / TL::TX) * (L::D == 3 ? (g.ny + TL::TY - 1) / TL::TY : 1);
     const int nm = L::D == 3 ? g.nz : g.ny;
-    auto items = [&](int c) { return tiles * ((nm + c - 1) / c); };
-    int chunk = TL::CHUNK;
-    for (int c : {32, 24, 16, 12, 8}) {
-        if (c >= chunk || items(chunk) >= slots) continue;
-        if (items(c) > slots) break;
-        chunk = c;
+    int best = TL::CHUNK;
+    long long best_cost = -1;
+    for (int c : {64, 48, 32, 24, 16, 12, 8}) {
+        const int planes = c < nm ? c : nm;
+        const long long items = tiles * ((nm + planes - 1) / planes);
+        const long long cost = (items + slots - 1) / slots * (planes + 3);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = planes;
+        }
     }
-    return chunk;
+    return best;
 }
 
 template <class L, class S>
