@@ -767,7 +767,8 @@ hipError_t launch_fused_step(const SweepArgs& a, StateP<S> A, StateP<S> B, int c
 
 // Planes per work item for a grid on a device with `cus` compute units. A work item costs about
 // its planes plus three (a chunk's first planes recompute what the previous chunk's last ones
-// computed, so the states do not depend on the choice), and the items run in rounds of as many
+// computed; the choice moves the states only through which tile code covers a plane, to
+// rounding), and the items run in rounds of as many
 // workgroups as the chip holds at once; the chunk minimising rounds x (planes + 3) over 64, 48, 32,
 // 24, 16, 12 and 8 planes is taken, the longer one on a tie. Measured sweep times order the
 // chunks as this estimate does on 384x192x192, 384x192x96, 256x128x128 (FP32) and on 384x192x192
