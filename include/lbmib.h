@@ -104,7 +104,9 @@ size_t lbm_workspace_bytes(const lbm_params* p);
 /* Create a handle on the current HIP device. dev_workspace: caller-owned device memory of at
  * least lbm_workspace_bytes(p) bytes, 256-byte aligned. hip_stream: a hipStream_t (NULL = the
  * default stream). The state is set to the free-stream equilibrium f = f^eq(rho_inf, u_inf, T_inf)
- * (Eq. (A.3)), rho E = rho_inf (|u_inf|^2/2 + Cv T_inf), zero force history.
+ * (Eq. (A.3)), rho E = rho_inf (|u_inf|^2/2 + Cv T_inf), zero force history. The fused sweep's
+ * planes per work item are chosen here for the grid and the device's compute units; the
+ * environment variable LBMIB_FUSED_CHUNK, if set to a positive integer, overrides the choice.
  * Errors: LBM_E_INVAL (dim, sizes, tau-bar <= 1/2, rest population of Eq. (A.3) negative at
  * T_inf, non-finite values), LBM_E_NOMEM (bytes too small), LBM_E_HIP. */
 int lbm_init_grid(const lbm_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
