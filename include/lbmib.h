@@ -293,8 +293,11 @@ int lbm_refine_prolong(lbm_refine* r);
 /* Enqueue n coupled steps (with every nested level, see lbm_refine_nest). The last one leaves in
  * the coarse handle the residual (lbm_residual) between the coarse states before and after it,
  * restriction included. Asynchronous. From three steps on, pairs of coupled steps replay a HIP
- * graph captured on the first such call (again after a state index or a body changed); the graph
- * and its capture stream belong to the coupling and are freed by lbm_refine_destroy.
+ * graph captured on the first such call (again after a state index or a body changed). Within a
+ * coupled step the coarse step runs on a second stream of the coupling beside the first fine
+ * step; events join it before the band refill, so all work stays ordered on the handles' stream.
+ * The graph, the streams and the events belong to the coupling and are freed by
+ * lbm_refine_destroy.
  * Errors: LBM_E_INVAL (n < 0, a body requirement broken, a nested coupling), LBM_E_HIP. */
 int lbm_refine_step(lbm_refine* r, int n);
 

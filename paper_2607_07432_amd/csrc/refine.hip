@@ -262,6 +262,10 @@ struct lbm_refine {
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t cap_stream = nullptr;
     std::vector<long long> graph_key;
+    // The coarse step of a coupled step runs on `side` beside the first fine step; ev_fork and
+    // ev_join order it within the coupled step.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::string err;
 };
 
@@ -309,15 +313,32 @@ int check_bodies(lbm_refine* r) {
 // of the nested coupling if there is one) each followed by its band refill, then the restriction.
 int coupled_step(lbm_refine* r) {
     lbm_handle *c = r->coarse, *f = r->fine;
-    if (int rc = step_handle(c, 1, false)) return rfail(r, rc, std::string("coarse step: ") + c->err);
+    // The coarse step and the first fine step are independent (the fine step reads the fine state
+    // alone, whose band the previous coupled step refilled): the coarse step runs on the side
+    // stream beside it, each grid then filling the part of the chip the other leaves, and the
+    // band refill after the first fine step waits for both.
+    const hipStream_t main = c->stream;
+    hipError_t e = hipEventRecord(r->ev_fork, main);
+    if (e == hipSuccess) e = hipStreamWaitEvent(r->side, r->ev_fork, 0);
+    if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("coarse step fork: ") + hipGetErrorString(e));
+    c->stream = r->side;
+    const int crc = step_handle(c, 1, false);
+    c->stream = main;
+    if (crc) return rfail(r, crc, std::string("coarse step: ") + c->err);
+    e = hipEventRecord(r->ev_join, r->side);
+    if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("coarse step join: ") + hipGetErrorString(e));
     for (int k = 1; k <= 2; ++k) {
         if (r->child) {
             if (int rc = coupled_step(r->child)) return rfail(r, rc, "inner level: " + r->child->err);
         } else if (int rc = step_handle(f, 1, false)) {
             return rfail(r, rc, std::string("fine step: ") + f->err);
         }
+        if (k == 1) {
+            e = hipStreamWaitEvent(main, r->ev_join, 0);
+            if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("coarse step join: ") + hipGetErrorString(e));
+        }
         // coarse: the previous state is the one before this coupled step, the current one after it
-        hipError_t e = dispatch(c, [&](auto L, auto S) {
+        e = dispatch(c, [&](auto L, auto S) {
             using LT = decltype(L);
             using ST = decltype(S);
             // at k = 2 the band takes the coarse state after the step alone
@@ -331,7 +352,7 @@ int coupled_step(lbm_refine* r) {
         });
         if (e != hipSuccess) return rfail(r, LBM_E_HIP, std::string("refine band: ") + hipGetErrorString(e));
     }
-    hipError_t e = dispatch(c, [&](auto L, auto S) {
+    e = dispatch(c, [&](auto L, auto S) {
         using LT = decltype(L);
         using ST = decltype(S);
         if (r->g.nrest > 0)
@@ -474,6 +495,13 @@ int lbm_refine_create(lbm_handle* coarse, lbm_handle* fine, const int* origin, i
     if (fine->args.fs.e_ref != q.e_ref) return rfail(nullptr, LBM_E_INVAL, "energy references differ");
     lbm_refine* r = new (std::nothrow) lbm_refine();
     if (!r) return rfail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    hipError_t se = hipStreamCreateWithFlags(&r->side, hipStreamNonBlocking);
+    if (se == hipSuccess) se = hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming);
+    if (se == hipSuccess) se = hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming);
+    if (se != hipSuccess) {
+        lbm_refine_destroy(r);
+        return rfail(nullptr, LBM_E_HIP, std::string("side stream: ") + hipGetErrorString(se));
+    }
     r->coarse = coarse;
     r->fine = fine;
     r->g = g;
@@ -561,6 +589,9 @@ void lbm_refine_destroy(lbm_refine* r) {
     if (r->child) r->child->parent = nullptr;
     if (r->graph_exec) hipGraphExecDestroy(r->graph_exec);
     if (r->cap_stream) hipStreamDestroy(r->cap_stream);
+    if (r->side) hipStreamDestroy(r->side);
+    if (r->ev_fork) hipEventDestroy(r->ev_fork);
+    if (r->ev_join) hipEventDestroy(r->ev_join);
     delete r;
 }
 
