@@ -315,8 +315,8 @@ int coupled_step(lbm_refine* r) {
     lbm_handle *c = r->coarse, *f = r->fine;
     // The coarse step and the first fine step are independent (the fine step reads the fine state
     // alone, whose band the previous coupled step refilled): the coarse step runs on the side
-    // stream beside it, each grid then filling the part of the chip the other leaves, and the
-    // band refill after the first fine step waits for both.
+    // stream beside it, so that the work items of both sweeps share the chip, and the band refill
+    // after the first fine step waits for both.
     const hipStream_t main = c->stream;
     hipError_t e = hipEventRecord(r->ev_fork, main);
     if (e == hipSuccess) e = hipStreamWaitEvent(r->side, r->ev_fork, 0);
